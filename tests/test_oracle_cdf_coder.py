@@ -1,0 +1,123 @@
+"""Pins of the oracle's CDF tables and reference rANS coder (CPU only)."""
+import mpmath
+import numpy as np
+import pytest
+import scipy.special
+
+import oracle as O
+
+mpmath.mp.dps = 50
+
+
+def _random_params(rng, n, K=3, extreme=True):
+    logits = rng.normal(0, 3, (n, K))
+    w = np.exp(logits - logits.max(1, keepdims=True))
+    w /= w.sum(1, keepdims=True)
+    mu = rng.uniform(-20, 20, (n, K))
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(8.0), (n, K)))
+    if extreme:
+        mu[: n // 4] = rng.uniform(-90, 90, (n // 4, K))
+        sg[n // 4: n // 2] = rng.choice([0.11, 0.2, 40.0, 300.0], (n // 2 - n // 4, K))
+    return np.concatenate([w, mu, sg], 1)
+
+
+def _exact_row(p, cfg):
+    """High-precision floor(F_max * C_j) straight from the definition."""
+    K = cfg["mix_k"]
+    Ns = cfg["sym_max"] - cfg["sym_min"] + 1
+    T = 1 << cfg["cdf_bits"]
+    Fmax = T - Ns
+    row = [0]
+    wsum = mpmath.fsum(mpmath.mpf(float(p[k])) for k in range(K))
+    for j in range(1, Ns):
+        b = mpmath.mpf(cfg["sym_min"] + j) - mpmath.mpf("0.5")
+        ws = [mpmath.mpf(float(p[k])) for k in range(K)]
+        zs = [(b - mpmath.mpf(float(p[K + k]))) / mpmath.mpf(float(p[2 * K + k])) for k in range(K)]
+        c = mpmath.fsum(ws[k] * mpmath.ncdf(zs[k]) for k in range(K)) / wsum
+        if c <= mpmath.mpf("0.5"):
+            row.append(j + int(mpmath.floor(Fmax * c)))
+        else:
+            # floor(F (1 - t)) = F - ceil(F t); t = 1 - c from the upper tails, which
+            # keeps its digits where c itself rounds to 1 even at 50 digits.
+            t = mpmath.fsum(ws[k] * mpmath.ncdf(-zs[k]) for k in range(K)) / wsum
+            row.append(j + Fmax - int(mpmath.ceil(Fmax * t)))
+    row.append(T)
+    return np.array(row, np.int64)
+
+
+def test_cdf_mixture_matches_high_precision(cfg_small):
+    rng = np.random.default_rng(21)
+    p = _random_params(rng, 24)
+    got = O.cdf_tables(p, cfg_small)
+    for n in range(p.shape[0]):
+        np.testing.assert_array_equal(got[n], _exact_row(p[n], cfg_small), err_msg=str(p[n]))
+
+
+def test_cdf_single_gaussian_matches_ndtr(cfg_small):
+    cfg = dict(cfg_small, mix_k=1)
+    rng = np.random.default_rng(22)
+    mu = rng.uniform(-30, 30, 40)
+    sg = np.exp(rng.uniform(np.log(0.2), np.log(20), 40))
+    p = np.stack([np.ones(40), mu, sg], 1)
+    got = O.cdf_tables(p, cfg)
+    b = np.arange(1, 129) - 64.5
+    c = scipy.special.ndtr((b[None] - mu[:, None]) / sg[:, None])
+    # Away from the upper tail (where 1 - c loses digits in float64) the floor agrees.
+    ok = c < 0.5
+    want = np.arange(1, 129)[None] + np.floor(65407 * c)
+    assert np.array_equal(got[:, 1:129][ok], want[ok])
+    for n in range(4):
+        np.testing.assert_array_equal(got[n], _exact_row(p[n], cfg))
+
+
+def test_cdf_invariants_on_extreme_params(cfg_small):
+    rng = np.random.default_rng(23)
+    p = _random_params(rng, 4000)
+    cdf = O.cdf_tables(p, cfg_small)
+    assert cdf.shape == (4000, 130)
+    assert np.all(cdf[:, 0] == 0) and np.all(cdf[:, 129] == 65536)
+    freq = np.diff(cdf, axis=1)
+    assert np.all(freq >= 1)
+    assert np.all(freq.sum(1) == 65536)
+    u16 = O.cdf_to_u16(cdf)
+    assert u16.dtype == np.uint16 and np.all(u16[:, 129] == 0)
+
+
+def test_cdf_concentrates_mass_near_mean(cfg_small):
+    # One narrow component at mu = 3: symbol 3 gets almost all of the mass.
+    p = np.array([[1.0, 0.0, 0.0, 3.0, 0.0, 0.0, 0.11, 1.0, 1.0]])
+    cdf = O.cdf_tables(p, cfg_small)[0]
+    freq = np.diff(cdf)
+    assert np.argmax(freq) == 3 + 64
+    assert freq[3 + 64] > 65536 - 200
+
+
+def _sample(rng, cdf):
+    u = rng.integers(0, 65536, cdf.shape[0])
+    return np.array([np.searchsorted(cdf[n], u[n], side="right") - 1 for n in range(cdf.shape[0])])
+
+
+def test_rans_reference_roundtrip_and_length(cfg_small):
+    rng = np.random.default_rng(24)
+    p = _random_params(rng, 3000, extreme=False)
+    cdf = O.cdf_tables(p, cfg_small)
+    idx = _sample(rng, cdf)
+    data = O.rans_encode_ref(O.cdf_to_u16(cdf), idx)
+    back = O.rans_decode_ref(O.cdf_to_u16(cdf), data, len(idx))
+    assert np.array_equal(back, idx)
+    ideal = O.ideal_bits(cdf, idx)
+    assert 8 * len(data) <= ideal * 1.002 + 64
+    assert 8 * len(data) >= ideal - 1
+
+
+def test_rans_reference_edge_cases(cfg_small):
+    rng = np.random.default_rng(25)
+    p = _random_params(rng, 50)
+    cdf = O.cdf_to_u16(O.cdf_tables(p, cfg_small))
+    # Empty stream, extreme symbols, truncation.
+    assert list(O.rans_decode_ref(cdf[:0], O.rans_encode_ref(cdf[:0], []), 0)) == []
+    idx = np.array([0, 128] * 25)
+    data = O.rans_encode_ref(cdf, idx)
+    assert np.array_equal(O.rans_decode_ref(cdf, data, 50), idx)
+    with pytest.raises(ValueError):
+        O.rans_decode_ref(cdf, data[:3], 50)

@@ -1,0 +1,76 @@
+"""Random-init weight blob and its manifest.
+
+The blob is a flat little-endian float32 array: the tensors of `manifest(cfg)`
+concatenated in manifest order, each conv as weight [Cout][Cin][3][3] followed
+by bias [Cout].  Every conv is drawn from one numpy Generator seeded with
+cfg["seed_weights"], weight then bias, uniform on +-1/sqrt(9*Cin).
+
+Manifest order:
+  1. four lifting filters P_row, U_row, P_col, U_col, each `lift_layers` convs:
+     1 -> lift_ch, (lift_ch -> lift_ch) x (lift_layers - 2), lift_ch -> 1;
+  2. the ConvLSTM gate conv, (1 + ctx_ch) -> 4*ctx_ch, gate blocks in the order
+     input, forget, cell, output; input channels [previous subband, hidden];
+  3. sixteen step stacks, subband type t in (LL, HL, LH, HH) outer, coding step
+     g in 0..3 inner, each `ctx_layers` convs: Cin_g -> ctx_ch,
+     (ctx_ch -> ctx_ch) x (ctx_layers - 2), ctx_ch -> 3*mix_k, where Cin_0 =
+     ctx_ch and Cin_g = 1 + ctx_ch for g >= 1 with channel 0 the symbol channel.
+"""
+import numpy as np
+
+LIFT_NAMES = ("P_row", "U_row", "P_col", "U_col")
+TYPE_NAMES = ("LL", "HL", "LH", "HH")
+
+
+def _lift_chain(cfg):
+    C, L = cfg["lift_ch"], cfg["lift_layers"]
+    return [1] + [C] * (L - 1) + [1]
+
+
+def _ctx_chain(cfg, g):
+    C, L, K = cfg["ctx_ch"], cfg["ctx_layers"], cfg["mix_k"]
+    cin = C if g == 0 else C + 1
+    return [cin] + [C] * (L - 1) + [3 * K]
+
+
+def manifest(cfg):
+    """List of (name, shape) in blob order."""
+    out = []
+
+    def conv(prefix, cin, cout):
+        out.append((prefix + ".w", (cout, cin, 3, 3)))
+        out.append((prefix + ".b", (cout,)))
+
+    for nm in LIFT_NAMES:
+        ch = _lift_chain(cfg)
+        for l in range(len(ch) - 1):
+            conv(f"lift.{nm}.{l}", ch[l], ch[l + 1])
+    C = cfg["ctx_ch"]
+    conv("lstm", 1 + C, 4 * C)
+    for t in TYPE_NAMES:
+        for g in range(4):
+            ch = _ctx_chain(cfg, g)
+            for l in range(len(ch) - 1):
+                conv(f"ctx.{t}.{g}.{l}", ch[l], ch[l + 1])
+    return out
+
+
+def make_weights(cfg):
+    """Dict name -> float32 array, drawn in manifest order."""
+    rng = np.random.default_rng(cfg["seed_weights"])
+    out = {}
+    pending_bound = None
+    for name, shape in manifest(cfg):
+        if name.endswith(".w"):
+            pending_bound = 1.0 / np.sqrt(9.0 * shape[1])
+        out[name] = rng.uniform(-pending_bound, pending_bound, shape).astype(np.float32)
+    return out
+
+
+def pack_weights(cfg, weights):
+    """Flat float32 blob in manifest order."""
+    return np.concatenate([np.ascontiguousarray(weights[n], np.float32).ravel()
+                           for n, _ in manifest(cfg)])
+
+
+def weights_nbytes(cfg):
+    return 4 * sum(int(np.prod(s)) for _, s in manifest(cfg))
