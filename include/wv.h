@@ -1,0 +1,226 @@
+/*
+ * wv.h - C ABI of the MI355X (gfx950) four-step learned-wavelet decode path.
+ *
+ * Method: A. Meyer, S. Prativadibhayankaram, A. Kaup, "Efficient Learned
+ * Wavelet Image and Video Coding", ICIP 2024 (arXiv 2405.12631).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Device memory is owned by the caller and passed as raw device pointers.
+ *   The library allocates no device memory; it owns only host-side handles.
+ * - Every GPU entry point enqueues work asynchronously on the caller's
+ *   stream (a hipStream_t passed as void*, NULL = the default stream) and
+ *   returns before the work finishes.  Inputs must stay valid until then.
+ * - Return value: WV_OK (0) or a negative WV_E* code.  wv_last_error()
+ *   returns a thread-local message for the last failure.  No entry point
+ *   exits, aborts or throws.
+ * - Shapes are checked on the host before any launch.  H and W must be
+ *   divisible by 2^levels (WV_ESHAPE otherwise).  A device fault is reported
+ *   as WV_EDEVICE by the call that observes it.
+ * - "Plane": one colour component (Sec. 3.1 codes each YCbCr component as
+ *   its own plane).  nplanes planes of one size are processed per call; all
+ *   planes share the model.
+ * - Subband order is the coding order LL_J, HL_J, LH_J, HH_J, ..., HL_1,
+ *   LH_1, HH_1 (Sec. 3.1, Fig. 1; Fig. 11 caption).  A plane's quantised
+ *   symbols are packed subband after subband, each row-major:
+ *   q[plane][offset_i + r * w_i + c], offsets from wv_layout().
+ * - Coding step g of a subband codes the positions with
+ *   2 * (r mod 2) + (c mod 2) == g, in raster order (Sec. 3.2, Fig. 3:
+ *   four steps, a quarter of the positions each, 0/2/6/8 coded 3x3
+ *   neighbours).  n_g = ceil((h - g/2) / 2) * ceil((w - g%2) / 2).
+ */
+#ifndef WV_H
+#define WV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WV_OK = 0,
+    WV_EINVAL = -1,       /* bad argument (null pointer, bad enum, bad config) */
+    WV_ESHAPE = -2,       /* image or buffer shape not supported */
+    WV_EORDER = -3,       /* subband/step out of range */
+    WV_EDEVICE = -4,      /* HIP runtime error or device fault */
+    WV_ECORRUPT = -5,     /* corrupt or truncated bitstream */
+    WV_EUNSUPPORTED = -6, /* configuration the kernels do not implement */
+    WV_ENOMEM = -7        /* caller-provided buffer too small */
+};
+
+typedef enum { WV_FP32 = 0, WV_BF16 = 1, WV_FP8 = 2 } wv_precision;
+
+/* Model hyper-parameters.  Sec. 3.1 (lifting), Sec. 3.2 (context model). */
+typedef struct wv_config {
+    int levels;      /* J decomposition levels (3J+1 subbands)                 */
+    int lift_ch;     /* channels inside a predict/update filter (16 or 32)     */
+    int lift_layers; /* conv3x3 layers per predict/update filter (>= 2)        */
+    int ctx_ch;      /* C: ConvLSTM hidden channels = step-stack width (32/64) */
+    int ctx_layers;  /* conv3x3 layers per coding-step stack (>= 2)            */
+    int mix_k;       /* K Gaussian components per coefficient (1..4)           */
+    int sym_min;     /* symbol alphabet [sym_min, sym_max], at most 255 symbols */
+    int sym_max;
+    int cdf_bits;    /* CDF precision: tables sum to 2^cdf_bits (16)           */
+    float sigma_min; /* lower bound of the mixture scales, symbol units        */
+    int lift_int;    /* 1: predict/update outputs rounded (lossless lifting)   */
+} wv_config;
+
+/* One subband of the packed layout. type: 0 LL, 1 HL, 2 LH, 3 HH. */
+typedef struct wv_subband {
+    int h, w, level, type;
+    long long offset; /* first coefficient within a plane */
+} wv_subband;
+
+typedef struct wv_model wv_model;
+
+const char* wv_last_error(void);
+int wv_version(void);
+
+/*
+ * Weight blob.  A flat float32 array, tensors in this order, each conv as
+ * weight [Cout][Cin][3][3] then bias [Cout]:
+ *   P_row, U_row, P_col, U_col: lift_layers convs each,
+ *       1 -> lift_ch, lift_ch -> lift_ch (lift_layers - 2 times), lift_ch -> 1;
+ *   ConvLSTM gates: (1 + ctx_ch) -> 4 ctx_ch, gate blocks input, forget,
+ *       cell, output; input channel 0 the previous subband's symbols;
+ *   16 step stacks, subband type LL, HL, LH, HH (outer) x step 0..3 (inner),
+ *       ctx_layers convs each: Cin_g -> ctx_ch, ctx_ch -> ctx_ch
+ *       (ctx_layers - 2 times), ctx_ch -> 3K; Cin_0 = ctx_ch, Cin_g = 1 + ctx_ch
+ *       for g >= 1 with channel 0 the current subband's coded symbols.
+ * wv_weights_count: number of floats of that blob for cfg.
+ */
+int wv_weights_count(const wv_config* cfg, long long* n_floats);
+
+/* Bytes of device memory the caller provides to wv_model_create for the
+ * kernels' repacked weights. */
+int wv_pack_bytes(const wv_config* cfg, int precision, size_t* bytes);
+
+/*
+ * Build a model handle.  d_weights: the blob above, in device memory
+ * (read once, synchronously on `stream`, and not referenced afterwards).
+ * d_pack: caller-owned device buffer of wv_pack_bytes() bytes that the model
+ * reads for its whole lifetime.  The handle is immutable; concurrent calls on
+ * different streams are safe if they use different workspaces.
+ */
+int wv_model_create(const wv_config* cfg, const float* d_weights, long long n_floats,
+                    int precision, void* d_pack, size_t pack_bytes, void* stream,
+                    wv_model** out);
+void wv_model_destroy(wv_model* m);
+
+/* Subband layout of an H x W plane: up to `cap` entries in coding order and the
+ * number of coefficients per plane (= H * W). */
+int wv_layout(const wv_config* cfg, int H, int W, wv_subband* out, int cap,
+              long long* coefs_per_plane);
+
+/* n_g of coding step `step` of an h x w subband. */
+long long wv_group_count(int h, int w, int step);
+
+/*
+ * Device workspace sizes for nplanes planes of H x W:
+ *   state_bytes   - ConvLSTM state (h, c), kept between wv_context_params calls;
+ *   scratch_bytes - temporary memory of any single call (analyze, context,
+ *                   synthesize); contents are not kept between calls.
+ */
+int wv_workspace_bytes(const wv_model* m, int nplanes, int H, int W,
+                       size_t* state_bytes, size_t* scratch_bytes);
+
+/*
+ * Analysis transform and quantisation (encoder side).  Sec. 3.1, Fig. 2:
+ * J levels of 1-D lifting row-wise then column-wise, HP = odd - P(even),
+ * LP = even + U(HP), P(z) = z + N_P(z), U(z) = z/2 + N_U(z); then
+ * q = clamp(round_half_even(y * Delta), sym_min, sym_max), Delta_L for LL_J,
+ * Delta_H for the rest.
+ *   d_x8   : uint8 planes [nplanes][H][W] (centred as x - 128), or NULL;
+ *   d_xf   : float planes [nplanes][H][W] already centred, used if d_x8 NULL;
+ *   d_q    : int16 [nplanes][H*W] packed symbols (output);
+ *   d_y    : optional float [nplanes][H*W] packed unquantised subbands;
+ *   d_clip : optional int32 counter; += number of clamped coefficients
+ *            (the caller zeroes it).
+ */
+int wv_analyze(const wv_model* m, const uint8_t* d_x8, const float* d_xf, int nplanes,
+               int H, int W, float delta_L, float delta_H, void* d_scratch,
+               int16_t* d_q, float* d_y, int* d_clip, void* stream);
+
+/*
+ * Entropy parameters of coding step `step` of subband `subband` (Sec. 3.2).
+ * step == 0 first advances the ConvLSTM long context (h, c) in d_state from
+ * the previous subband to this one (input: the previous subband's symbols,
+ * state and input upsampled x2 when the resolution doubles; zero state and
+ * input for subband 0).  The step stack then reads the long context and, for
+ * step >= 1, the symbols of steps < step of this subband; it never reads
+ * positions of later steps or later subbands (causality).
+ * Calls must come in coding order per plane set: (0,0), (0,1), ..., (0,3),
+ * (1,0), ...; step 0 of subband i needs subband i-1 fully decoded in d_q.
+ *   d_params : float [nplanes][n_g][3K] = (w_0..w_{K-1}, mu_0.., sigma_0..),
+ *              w = softmax, mu raw, sigma = max(softplus, sigma_min),
+ *              in symbol units.
+ */
+int wv_context_params(const wv_model* m, const int16_t* d_q, int nplanes, int H, int W,
+                      int subband, int step, float* d_state, void* d_scratch,
+                      float* d_params, void* stream);
+
+/*
+ * 16-bit CDF tables of n discretised K-component Gaussian mixtures.  The
+ * paper arithmetic-codes the symbols with the estimated distribution
+ * (Sec. 3.1); the table format is this library's:
+ *   N_s = sym_max - sym_min + 1, F_max = 2^cdf_bits - N_s,
+ *   C_j = sum_k w_k Phi((sym_min + j - 0.5 - mu_k) / sigma_k) / sum_k w_k,
+ *   F_j = floor(F_max * C_j) (exact value: from the upper tail where
+ *   C_j > 1/2, never F_max), running maximum, cdf[j] = j + F_j, j = 0..N_s-1;
+ *   cdf[N_s] = 2^cdf_bits stored as 0 (mod 2^16).  Every symbol has
+ *   frequency >= 1.
+ *   d_params : float [n][3K];  d_cdf : uint16 [n][N_s + 1].
+ * Requires cdf_bits == 16 and N_s <= 255.
+ */
+int wv_cdf_tables(const float* d_params, long long n, int mix_k, int sym_min, int sym_max,
+                  int cdf_bits, uint16_t* d_cdf, void* stream);
+
+/* Write decoded symbol indices (symbol - sym_min) of step `step` of subband
+ * `subband` into the packed symbols: d_sym uint8 [nplanes][n_g]. */
+int wv_scatter_symbols(const wv_config* cfg, const uint8_t* d_sym, int nplanes, int H, int W,
+                       int subband, int step, int16_t* d_q, void* stream);
+
+/* Encoder side: read the symbol indices of one step, d_sym uint8 [nplanes][n_g]. */
+int wv_gather_symbols(const wv_config* cfg, const int16_t* d_q, int nplanes, int H, int W,
+                      int subband, int step, uint8_t* d_sym, void* stream);
+
+/*
+ * Dequantisation and synthesis (Sec. 3.1): y_hat = q / Delta, then the exact
+ * inverse of wv_analyze level by level, then + 128.
+ *   d_q or d_y (float packed subbands, used when d_q is NULL);
+ *   d_xhat : float [nplanes][H][W];  d_u8 : optional uint8 clamp(rint(x_hat)).
+ */
+int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int nplanes,
+                  int H, int W, float delta_L, float delta_H, void* d_scratch,
+                  float* d_xhat, uint8_t* d_u8, void* stream);
+
+/*
+ * Temporal Haar lifting over a GOP of T = 2^levels frames of n floats each
+ * (lifting form of Sec. 3.3 without motion compensation): H = f_odd - f_even,
+ * L = f_even + H/2, recursively on L.  Subband order: L_J, H_J, H_{J-1} (2),
+ * ..., H_1 (T/2).  In place on d_frames [T][n]; T a power of two <= 32.
+ */
+int wv_temporal_haar_forward(float* d_frames, int T, long long n, void* stream);
+int wv_temporal_haar_inverse(float* d_frames, int T, long long n, void* stream);
+
+/*
+ * Host rANS coder (no GPU).  Byte-wise renormalising rANS with a 32-bit state
+ * in [2^23, 2^31) and M = 2^16: symbols are encoded last to first so the
+ * decoder emits them in raster order; the stream starts with the final state
+ * (4 bytes, little endian).  cdf rows as produced by wv_cdf_tables (row
+ * stride nsym + 1, final entry 0 meaning 2^16).
+ *   encode: out capacity `cap`; *len receives the stream length;
+ *           WV_ENOMEM if cap is too small.
+ *   decode: WV_ECORRUPT on a truncated or inconsistent stream.
+ */
+int wv_rans_encode(const uint16_t* cdf, int nsym, const uint8_t* sym, long long n,
+                   uint8_t* out, size_t cap, size_t* len);
+int wv_rans_decode(const uint16_t* cdf, int nsym, long long n, const uint8_t* in, size_t len,
+                   uint8_t* sym_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WV_H */

@@ -33,14 +33,16 @@ def conv3x3(x, w, b):
     """
     x = np.asarray(x, np.float64)
     w = np.asarray(w, np.float64)
-    N, H, W, _ = x.shape
+    N, H, W, Cin = x.shape
+    Cout = w.shape[0]
     xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
-    out = np.empty((N, H, W, w.shape[0]), np.float64)
+    out = np.empty((N * H * W, Cout), np.float64)
     out[...] = np.asarray(b, np.float64)
     for dy in range(3):
         for dx in range(3):
-            out += xp[:, dy:dy + H, dx:dx + W, :] @ w[:, :, dy, dx].T
-    return out
+            tap = np.ascontiguousarray(xp[:, dy:dy + H, dx:dx + W, :]).reshape(-1, Cin)
+            out += tap @ np.ascontiguousarray(w[:, :, dy, dx].T)
+    return out.reshape(N, H, W, Cout)
 
 
 def conv3x3_direct(x, w, b):

@@ -1,0 +1,326 @@
+"""Python runtime over libwv.so: model upload, workspaces, the encode and
+decode drivers, and the bitstream container.
+
+Every arithmetic step of the path runs in the HIP library (or, for the
+entropy coder, in its host C++ code); this module only allocates torch
+buffers, sequences the calls and moves bytes.  There is no fallback: if the
+library is missing the first call raises.
+"""
+import ctypes
+import hashlib
+import struct
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_byref = ctypes.byref
+
+
+def make_config(cfg):
+    """wv_config from a workload dict (wvgen.configs layout)."""
+    return L.wv_config(levels=cfg["levels"], lift_ch=cfg["lift_ch"], lift_layers=cfg["lift_layers"],
+                       ctx_ch=cfg["ctx_ch"], ctx_layers=cfg["ctx_layers"], mix_k=cfg["mix_k"],
+                       sym_min=cfg["sym_min"], sym_max=cfg["sym_max"], cdf_bits=cfg["cdf_bits"],
+                       sigma_min=cfg["sigma_min"], lift_int=int(cfg.get("lift_int", 0)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Model:
+    """A model handle: weights uploaded and repacked on the current device."""
+
+    def __init__(self, cfg, blob, precision=L.WV_FP32, device="cuda"):
+        self.cfg = dict(cfg)
+        self.c = make_config(cfg)
+        self.precision = precision
+        blob = np.ascontiguousarray(blob, np.float32)
+        n = ctypes.c_longlong()
+        L.call("wv_weights_count", _byref(self.c), _byref(n))
+        if n.value != blob.size:
+            raise ValueError(f"blob has {blob.size} floats, config needs {n.value}")
+        self.blob_sha = hashlib.sha256(blob.tobytes()).digest()
+        self.d_blob = torch.from_numpy(blob).to(device)
+        nb = ctypes.c_size_t()
+        L.call("wv_pack_bytes", _byref(self.c), precision, _byref(nb))
+        self.d_pack = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        L.call("wv_model_create", _byref(self.c), _ptr(self.d_blob), n.value, precision,
+               _ptr(self.d_pack), nb.value, _stream(), _byref(h))
+        self.h = h
+        self.device = device
+        self.nsym = cfg["sym_max"] - cfg["sym_min"] + 1
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                L.lib().wv_model_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def layout(self, H, W):
+        n = 3 * self.cfg["levels"] + 1
+        arr = (L.wv_subband * n)()
+        coefs = ctypes.c_longlong()
+        L.call("wv_layout", _byref(self.c), H, W, arr, n, _byref(coefs))
+        return [dict(h=s.h, w=s.w, level=s.level, type=s.type, offset=s.offset) for s in arr]
+
+    @staticmethod
+    def group_count(h, w, g):
+        return int(L.lib().wv_group_count(h, w, g))
+
+    def deltas(self):
+        d = 1.0 / float(self.cfg["step"])
+        return d, d
+
+
+class Workspace:
+    """Device state and scratch for nplanes planes of H x W."""
+
+    def __init__(self, model, N, H, W):
+        sb, xb = ctypes.c_size_t(), ctypes.c_size_t()
+        L.call("wv_workspace_bytes", model.h, N, H, W, _byref(sb), _byref(xb))
+        self.N, self.H, self.W = N, H, W
+        self.state = torch.empty(sb.value // 4, dtype=torch.float32, device=model.device)
+        self.scratch = torch.empty(xb.value // 4, dtype=torch.float32, device=model.device)
+        self.lay = model.layout(H, W)
+        maxg = max(Model.group_count(s["h"], s["w"], 0) for s in self.lay)
+        K = model.cfg["mix_k"]
+        self.params = torch.empty(N * maxg * 3 * K, dtype=torch.float32, device=model.device)
+        self.cdf = torch.empty(N * maxg * (model.nsym + 1), dtype=torch.int16, device=model.device)
+        self.sym = torch.empty(N * maxg, dtype=torch.uint8, device=model.device)
+
+
+# ---------------------------------------------------------------------------
+# single calls
+# ---------------------------------------------------------------------------
+def analyze(model, x, ws, want_y=False):
+    """x: uint8 [N,H,W] or centred float [N,H,W] device tensor -> (q int16 [N,HW], y|None, clips)."""
+    N, H, W = x.shape
+    q = torch.empty((N, H * W), dtype=torch.int16, device=x.device)
+    y = torch.empty((N, H * W), dtype=torch.float32, device=x.device) if want_y else None
+    clip = torch.zeros(1, dtype=torch.int32, device=x.device)
+    dL, dH = model.deltas()
+    x8 = x if x.dtype == torch.uint8 else None
+    xf = x if x.dtype == torch.float32 else None
+    L.call("wv_analyze", model.h, _ptr(x8), _ptr(xf), N, H, W, dL, dH, _ptr(ws.scratch), _ptr(q),
+           _ptr(y), _ptr(clip), _stream())
+    return q, y, clip
+
+
+def context_params(model, q, ws, i, g, out=None):
+    """Parameters [N, n_g, 3K] of step g of subband i (q: int16 [N, HW] device)."""
+    s = ws.lay[i]
+    ng = Model.group_count(s["h"], s["w"], g)
+    K = model.cfg["mix_k"]
+    if out is None:
+        out = ws.params[:ws.N * ng * 3 * K]
+    L.call("wv_context_params", model.h, _ptr(q), ws.N, ws.H, ws.W, i, g, _ptr(ws.state),
+           _ptr(ws.scratch), _ptr(out), _stream())
+    return out.view(ws.N, ng, 3 * K)
+
+
+def cdf_tables(model, params, out=None):
+    """uint16 CDF rows (held in an int16 tensor) [n, nsym+1] for params [.., 3K]."""
+    K = model.cfg["mix_k"]
+    n = params.numel() // (3 * K)
+    if out is None:
+        out = torch.empty(n * (model.nsym + 1), dtype=torch.int16, device=params.device)
+    L.call("wv_cdf_tables", _ptr(params), n, K, model.cfg["sym_min"], model.cfg["sym_max"],
+           model.cfg["cdf_bits"], _ptr(out), _stream())
+    return out[:n * (model.nsym + 1)].view(n, model.nsym + 1)
+
+
+def scatter_symbols(model, sym, q, ws, i, g):
+    L.call("wv_scatter_symbols", _byref(model.c), _ptr(sym), ws.N, ws.H, ws.W, i, g, _ptr(q),
+           _stream())
+
+
+def gather_symbols(model, q, ws, i, g, out=None):
+    s = ws.lay[i]
+    ng = Model.group_count(s["h"], s["w"], g)
+    if out is None:
+        out = torch.empty(ws.N * ng, dtype=torch.uint8, device=q.device)
+    L.call("wv_gather_symbols", _byref(model.c), _ptr(q), ws.N, ws.H, ws.W, i, g, _ptr(out),
+           _stream())
+    return out[:ws.N * ng].view(ws.N, ng)
+
+
+def synthesize(model, ws, q=None, y=None, xhat=None, want_u8=False):
+    """q int16 [N,HW] (or float packed y) -> (xhat float [N,H,W], u8|None)."""
+    N, H, W = ws.N, ws.H, ws.W
+    dev = (q if q is not None else y).device
+    if xhat is None:
+        xhat = torch.empty((N, H, W), dtype=torch.float32, device=dev)
+    u8 = torch.empty((N, H, W), dtype=torch.uint8, device=dev) if want_u8 else None
+    dL, dH = model.deltas()
+    L.call("wv_synthesize", model.h, _ptr(q), _ptr(y), N, H, W, dL, dH, _ptr(ws.scratch),
+           _ptr(xhat), _ptr(u8), _stream())
+    return xhat, u8
+
+
+def temporal_haar(frames, inverse=False):
+    """In-place temporal Haar lifting of a float device tensor [T, ...]."""
+    T = frames.shape[0]
+    n = frames.numel() // T
+    L.call("wv_temporal_haar_inverse" if inverse else "wv_temporal_haar_forward", _ptr(frames), T,
+           n, _stream())
+    return frames
+
+
+def params_all(model, q, ws):
+    """Teacher-forced parameters of every (subband, step): list [i][g] of [N, n_g, 3K] copies."""
+    out = []
+    for i in range(len(ws.lay)):
+        row = []
+        for g in range(4):
+            row.append(context_params(model, q, ws, i, g).clone())
+        out.append(row)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# host coder
+# ---------------------------------------------------------------------------
+def rans_encode(cdf_u16, sym_u8, nsym):
+    """cdf_u16: numpy uint16 [n, nsym+1]; sym_u8: numpy uint8 [n] -> bytes."""
+    cdf_u16 = np.ascontiguousarray(cdf_u16, np.uint16)
+    sym_u8 = np.ascontiguousarray(sym_u8, np.uint8)
+    n = sym_u8.size
+    cap = 16 + 4 * n
+    buf = np.empty(cap, np.uint8)
+    ln = ctypes.c_size_t()
+    L.call("wv_rans_encode", cdf_u16.ctypes.data, nsym, sym_u8.ctypes.data, n, buf.ctypes.data, cap,
+           _byref(ln))
+    return buf[:ln.value].tobytes()
+
+
+def rans_decode(cdf_u16, data, n, nsym):
+    cdf_u16 = np.ascontiguousarray(cdf_u16, np.uint16)
+    out = np.empty(n, np.uint8)
+    src = np.frombuffer(data, np.uint8) if len(data) else np.zeros(1, np.uint8)
+    L.call("wv_rans_decode", cdf_u16.ctypes.data, nsym, n, src.ctypes.data, len(data),
+           out.ctypes.data)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# bitstream container
+# ---------------------------------------------------------------------------
+_MAGIC = b"WV01"
+_HDR = struct.Struct("<4sHHIIBBHff16sI")
+
+
+def pack_stream(model, N, H, W, streams):
+    """streams: list over planes of list over subbands of 4 byte strings."""
+    flat = [s for plane in streams for sub in plane for s in sub]
+    dL, dH = model.deltas()
+    hdr = _HDR.pack(_MAGIC, 1, N, H, W, model.cfg["levels"], model.precision, 0, dL, dH,
+                    model.blob_sha[:16], len(flat))
+    return hdr + struct.pack(f"<{len(flat)}I", *[len(s) for s in flat]) + b"".join(flat)
+
+
+def unpack_stream(model, data):
+    """-> (N, H, W, streams[plane][subband][step]); raises WvError(WV_ECORRUPT) on a bad container."""
+    def bad(msg):
+        return L.WvError(L.WV_ECORRUPT, msg)
+    if len(data) < _HDR.size:
+        raise bad("truncated header")
+    magic, ver, N, H, W, J, prec, _, dL, dH, sha, ns = _HDR.unpack_from(data, 0)
+    if magic != _MAGIC or ver != 1:
+        raise bad("not a wv bitstream")
+    if sha != model.blob_sha[:16] or J != model.cfg["levels"] or prec != model.precision:
+        raise bad("bitstream was written by another model")
+    nsub = 3 * J + 1
+    if ns != N * nsub * 4:
+        raise bad("stream count does not match the header")
+    off = _HDR.size + 4 * ns
+    if len(data) < off:
+        raise bad("truncated length table")
+    lens = struct.unpack_from(f"<{ns}I", data, _HDR.size)
+    if off + sum(lens) != len(data):
+        raise bad("stream lengths do not match the payload")
+    flat = []
+    for ln in lens:
+        flat.append(data[off:off + ln])
+        off += ln
+    streams = [[flat[(n * nsub + i) * 4:(n * nsub + i) * 4 + 4] for i in range(nsub)] for n in range(N)]
+    return N, H, W, streams
+
+
+# ---------------------------------------------------------------------------
+# encode / decode drivers
+# ---------------------------------------------------------------------------
+_pool = ThreadPoolExecutor(max_workers=8)
+
+
+def encode(model, planes, ws=None):
+    """uint8 planes [N,H,W] (numpy or device tensor) -> (bitstream bytes, q device tensor)."""
+    x = torch.as_tensor(planes).to(model.device)
+    N, H, W = x.shape
+    ws = ws or Workspace(model, N, H, W)
+    q, _, _ = analyze(model, x, ws)
+    streams = [[[None] * 4 for _ in ws.lay] for _ in range(N)]
+    for i, s in enumerate(ws.lay):
+        for g in range(4):
+            prm = context_params(model, q, ws, i, g)
+            cdf = cdf_tables(model, prm, out=ws.cdf)
+            sym = gather_symbols(model, q, ws, i, g, out=ws.sym)
+            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            sym_h = sym.cpu().numpy()
+            ng = sym_h.shape[1]
+            futs = [_pool.submit(rans_encode, cdf_h[n * ng:(n + 1) * ng], sym_h[n], model.nsym)
+                    for n in range(N)]
+            for n, f in enumerate(futs):
+                streams[n][i][g] = f.result()
+    return pack_stream(model, N, H, W, streams), q
+
+
+def decode(model, data, ws=None, want_u8=True):
+    """bitstream -> (xhat float [N,H,W], u8 [N,H,W] | None, q int16 [N,HW]) on the device."""
+    N, H, W, streams = unpack_stream(model, data)
+    ws = ws or Workspace(model, N, H, W)
+    q = torch.zeros((N, H * W), dtype=torch.int16, device=model.device)
+    for i, s in enumerate(ws.lay):
+        for g in range(4):
+            prm = context_params(model, q, ws, i, g)
+            cdf = cdf_tables(model, prm, out=ws.cdf)
+            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            ng = Model.group_count(s["h"], s["w"], g)
+            futs = [_pool.submit(rans_decode, cdf_h[n * ng:(n + 1) * ng], streams[n][i][g], ng,
+                                 model.nsym) for n in range(N)]
+            sym_h = np.stack([f.result() for f in futs]) if N else np.zeros((0, ng), np.uint8)
+            sym = ws.sym[:N * ng]
+            sym.copy_(torch.from_numpy(sym_h.reshape(-1)))
+            scatter_symbols(model, sym, q, ws, i, g)
+    xhat, u8 = synthesize(model, ws, q=q, want_u8=want_u8)
+    return xhat, u8, q
+
+
+def prepare_elided(model, q_known, ws):
+    """Per-step symbol indices of known q, gathered once before a timed coder-elided decode."""
+    return [[gather_symbols(model, q_known, ws, i, g).clone() for g in range(4)]
+            for i in range(len(ws.lay))]
+
+
+def decode_elided(model, syms, ws, q, xhat=None):
+    """The GPU part of decoding with the entropy coder elided: for every
+    (subband, step) the context model, its CDF tables and the scatter of that
+    step's symbols (taken from `syms` instead of the host coder), then
+    synthesis.  All launches are asynchronous on the current stream."""
+    for i in range(len(ws.lay)):
+        for g in range(4):
+            prm = context_params(model, q, ws, i, g)
+            cdf_tables(model, prm, out=ws.cdf)
+            scatter_symbols(model, syms[i][g], q, ws, i, g)
+    return synthesize(model, ws, q=q, xhat=xhat)[0]

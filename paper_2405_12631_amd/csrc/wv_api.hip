@@ -1,0 +1,728 @@
+// C ABI of the four-step learned-wavelet decode path (declarations and
+// documentation in include/wv.h).  Host code: argument checks, weight
+// repacking, workspace layout and the launch sequence of each call.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "wv_internal.h"
+
+using namespace wv;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(WV_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+extern "C" const char* wv_last_error(void) { return g_err.c_str(); }
+extern "C" int wv_version(void) { return 100; }
+
+// ---------------------------------------------------------------------------
+// config, blob manifest
+// ---------------------------------------------------------------------------
+static int check_cfg(const wv_config* c) {
+    if (!c) return fail(WV_EINVAL, "null config");
+    if (c->levels < 1 || c->levels > 8) return fail(WV_EINVAL, "levels must be 1..8");
+    if (c->lift_ch != 16 && c->lift_ch != 32) return fail(WV_EUNSUPPORTED, "lift_ch must be 16 or 32");
+    if (c->lift_layers < 2) return fail(WV_EINVAL, "lift_layers must be >= 2");
+    if (c->ctx_ch != 16 && c->ctx_ch != 32 && c->ctx_ch != 64)
+        return fail(WV_EUNSUPPORTED, "ctx_ch must be 16, 32 or 64");
+    if (c->ctx_layers < 2) return fail(WV_EINVAL, "ctx_layers must be >= 2");
+    if (c->mix_k < 1 || c->mix_k > 4) return fail(WV_EUNSUPPORTED, "mix_k must be 1..4");
+    const int nsym = c->sym_max - c->sym_min + 1;
+    if (nsym < 2 || nsym > 255) return fail(WV_EUNSUPPORTED, "alphabet must have 2..255 symbols");
+    if (c->sym_min < -32768 || c->sym_max > 32767) return fail(WV_EINVAL, "alphabet exceeds int16");
+    if (c->cdf_bits != 16) return fail(WV_EUNSUPPORTED, "cdf_bits must be 16");
+    if (!(c->sigma_min > 0.f)) return fail(WV_EINVAL, "sigma_min must be > 0");
+    return WV_OK;
+}
+
+namespace {
+
+struct ConvShape {
+    int cin, cout;
+    long long w_off, b_off;   // float offsets in the blob
+};
+
+struct Manifest {
+    std::vector<ConvShape> lift[4];   // P_row, U_row, P_col, U_col
+    ConvShape lstm;
+    std::vector<ConvShape> ctx[4][4]; // [type][step]
+    long long total = 0;
+};
+
+Manifest make_manifest(const wv_config& c) {
+    Manifest m;
+    long long off = 0;
+    auto conv = [&](int cin, int cout) {
+        ConvShape s{cin, cout, off, 0};
+        off += (long long)cout * cin * 9;
+        s.b_off = off;
+        off += cout;
+        return s;
+    };
+    for (int f = 0; f < 4; ++f) {
+        std::vector<int> ch;
+        ch.push_back(1);
+        for (int l = 0; l < c.lift_layers - 1; ++l) ch.push_back(c.lift_ch);
+        ch.push_back(1);
+        for (size_t l = 0; l + 1 < ch.size(); ++l) m.lift[f].push_back(conv(ch[l], ch[l + 1]));
+    }
+    m.lstm = conv(1 + c.ctx_ch, 4 * c.ctx_ch);
+    for (int t = 0; t < 4; ++t)
+        for (int g = 0; g < 4; ++g) {
+            std::vector<int> ch;
+            ch.push_back(g == 0 ? c.ctx_ch : 1 + c.ctx_ch);
+            for (int l = 0; l < c.ctx_layers - 1; ++l) ch.push_back(c.ctx_ch);
+            ch.push_back(3 * c.mix_k);
+            for (size_t l = 0; l + 1 < ch.size(); ++l) m.ctx[t][g].push_back(conv(ch[l], ch[l + 1]));
+        }
+    m.total = off;
+    return m;
+}
+
+// Host-side repacked model before upload.
+struct PackBuf {
+    std::vector<float> data;
+    size_t add(size_t nfloats) {   // 256-byte aligned sub-buffer
+        size_t off = (data.size() + 63) & ~(size_t)63;
+        data.resize(off + nfloats, 0.f);
+        return off;
+    }
+};
+
+struct MfmaRef { size_t w, wsym, bias; int cin, cout, nbt, has_sym; };
+struct VecRef { size_t w, bias; int ch; };
+
+// Original output channel of packed column nc.  LSTM: columns are grouped by
+// 64 = (input, forget, cell, output) x 16 channels so that one workgroup's
+// accumulators hold all four gates of the same channels.
+static int perm_col(int nc, int C, bool lstm) {
+    if (!lstm) return nc;
+    const int j = nc / 64, gate = (nc % 64) / 16, ch = 16 * j + nc % 16;
+    return gate * C + ch;
+}
+
+MfmaRef pack_mfma(PackBuf& pb, const float* blob, const ConvShape& s, int has_sym, bool lstm,
+                  int C) {
+    MfmaRef r;
+    r.cin = s.cin - has_sym;
+    r.cout = s.cout;
+    r.nbt = (s.cout + 15) / 16;
+    r.has_sym = has_sym;
+    const int CB = r.cin / 16;
+    const int cin_total = s.cin;
+    const float* W = blob + s.w_off;
+    const float* B = blob + s.b_off;
+    r.w = pb.add((size_t)9 * CB * r.nbt * 256);
+    r.wsym = has_sym ? pb.add((size_t)3 * r.nbt * 64) : 0;
+    r.bias = pb.add((size_t)r.nbt * 16);
+    float* pw = pb.data.data() + r.w;
+    for (int tap = 0; tap < 9; ++tap)
+        for (int cb = 0; cb < CB; ++cb)
+            for (int nb = 0; nb < r.nbt; ++nb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int t = 0; t < 4; ++t) {
+                        const int kk = lane >> 4, nn = lane & 15;
+                        const int k = 16 * cb + 4 * kk + t;
+                        const int nc = nb * 16 + nn;
+                        float v = 0.f;
+                        if (nc < s.cout) {
+                            const int o = perm_col(nc, C, lstm);
+                            v = W[((long long)o * cin_total + has_sym + k) * 9 + tap];
+                        }
+                        pw[(((size_t)(tap * CB + cb) * r.nbt + nb) * 64 + lane) * 4 + t] = v;
+                    }
+    if (has_sym) {
+        float* ps = pb.data.data() + r.wsym;
+        for (int chunk = 0; chunk < 3; ++chunk)
+            for (int nb = 0; nb < r.nbt; ++nb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int kk = lane >> 4, nn = lane & 15;
+                    const int tap = chunk * 4 + kk;
+                    const int nc = nb * 16 + nn;
+                    float v = 0.f;
+                    if (tap < 9 && nc < s.cout)
+                        v = W[((long long)perm_col(nc, C, lstm) * cin_total + 0) * 9 + tap];
+                    ps[((size_t)chunk * r.nbt + nb) * 64 + lane] = v;
+                }
+    }
+    float* pbias = pb.data.data() + r.bias;
+    for (int nc = 0; nc < s.cout; ++nc) pbias[nc] = B[perm_col(nc, C, lstm)];
+    return r;
+}
+
+VecRef pack_vec_first(PackBuf& pb, const float* blob, const ConvShape& s) {
+    VecRef r;
+    r.ch = s.cout;
+    r.w = pb.add((size_t)9 * s.cout);
+    r.bias = pb.add((size_t)s.cout);
+    for (int tap = 0; tap < 9; ++tap)
+        for (int ch = 0; ch < s.cout; ++ch)
+            pb.data[r.w + tap * s.cout + ch] = blob[s.w_off + (long long)ch * 9 + tap];
+    for (int ch = 0; ch < s.cout; ++ch) pb.data[r.bias + ch] = blob[s.b_off + ch];
+    return r;
+}
+
+VecRef pack_vec_last(PackBuf& pb, const float* blob, const ConvShape& s) {
+    VecRef r;
+    r.ch = s.cin;
+    r.w = pb.add((size_t)9 * s.cin);
+    r.bias = pb.add(4);
+    for (int tap = 0; tap < 9; ++tap)
+        for (int ch = 0; ch < s.cin; ++ch)
+            pb.data[r.w + tap * s.cin + ch] = blob[s.w_off + (long long)ch * 9 + tap];
+    pb.data[r.bias] = blob[s.b_off];
+    return r;
+}
+
+struct HostModel {
+    VecRef lift_first[4], lift_last[4];
+    std::vector<MfmaRef> lift_mid[4];
+    MfmaRef lstm;
+    std::vector<MfmaRef> ctx[4][4];
+};
+
+HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c) {
+    const Manifest mf = make_manifest(c);
+    HostModel hm;
+    for (int f = 0; f < 4; ++f) {
+        const auto& v = mf.lift[f];
+        hm.lift_first[f] = pack_vec_first(pb, blob, v.front());
+        for (size_t l = 1; l + 1 < v.size(); ++l)
+            hm.lift_mid[f].push_back(pack_mfma(pb, blob, v[l], 0, false, 0));
+        hm.lift_last[f] = pack_vec_last(pb, blob, v.back());
+    }
+    hm.lstm = pack_mfma(pb, blob, mf.lstm, 1, true, c.ctx_ch);
+    for (int t = 0; t < 4; ++t)
+        for (int g = 0; g < 4; ++g) {
+            const auto& v = mf.ctx[t][g];
+            for (size_t l = 0; l < v.size(); ++l)
+                hm.ctx[t][g].push_back(pack_mfma(pb, blob, v[l], (l == 0 && g > 0) ? 1 : 0, false, 0));
+        }
+    return hm;
+}
+
+}  // namespace
+
+struct wv_model {
+    wv_config cfg;
+    int precision;
+    VecLayer lift_first[4], lift_last[4];
+    std::vector<MfmaLayer> lift_mid[4];
+    MfmaLayer lstm;
+    std::vector<MfmaLayer> ctx[4][4];
+};
+
+extern "C" int wv_weights_count(const wv_config* cfg, long long* n_floats) {
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!n_floats) return fail(WV_EINVAL, "null output");
+    *n_floats = make_manifest(*cfg).total;
+    return WV_OK;
+}
+
+static size_t pack_floats(const wv_config& c) {
+    // Pack a zero blob to measure the layout size (host only, cheap).
+    const Manifest mf = make_manifest(c);
+    std::vector<float> zero((size_t)mf.total, 0.f);
+    PackBuf pb;
+    pack_all(pb, zero.data(), c);
+    return pb.data.size();
+}
+
+extern "C" int wv_pack_bytes(const wv_config* cfg, int precision, size_t* bytes) {
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (precision != WV_FP32) return fail(WV_EUNSUPPORTED, "only WV_FP32 is implemented");
+    if (!bytes) return fail(WV_EINVAL, "null output");
+    *bytes = pack_floats(*cfg) * sizeof(float);
+    return WV_OK;
+}
+
+extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, long long n_floats,
+                               int precision, void* d_pack, size_t pack_bytes, void* stream,
+                               wv_model** out) {
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (!d_weights || !d_pack || !out) return fail(WV_EINVAL, "null pointer");
+    if (precision != WV_FP32) return fail(WV_EUNSUPPORTED, "only WV_FP32 is implemented");
+    const Manifest mf = make_manifest(*cfg);
+    if (n_floats != mf.total)
+        return fail(WV_EINVAL, "weight blob has %lld floats, config needs %lld", n_floats, mf.total);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> blob((size_t)mf.total);
+    HIPCHK(hipMemcpyAsync(blob.data(), d_weights, blob.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    PackBuf pb;
+    HostModel hm = pack_all(pb, blob.data(), *cfg);
+    if (pb.data.size() * sizeof(float) > pack_bytes)
+        return fail(WV_ENOMEM, "pack buffer has %zu bytes, needs %zu", pack_bytes,
+                    pb.data.size() * sizeof(float));
+    HIPCHK(hipMemcpyAsync(d_pack, pb.data.data(), pb.data.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const float* base = (const float*)d_pack;
+    auto mfma = [&](const MfmaRef& r) {
+        return MfmaLayer{base + r.w, r.has_sym ? base + r.wsym : nullptr, base + r.bias,
+                         r.cin, r.cout, r.nbt, r.has_sym};
+    };
+    auto vec = [&](const VecRef& r) { return VecLayer{base + r.w, base + r.bias, r.ch}; };
+    wv_model* m = new wv_model();
+    m->cfg = *cfg;
+    m->precision = precision;
+    for (int f = 0; f < 4; ++f) {
+        m->lift_first[f] = vec(hm.lift_first[f]);
+        m->lift_last[f] = vec(hm.lift_last[f]);
+        for (auto& r : hm.lift_mid[f]) m->lift_mid[f].push_back(mfma(r));
+    }
+    m->lstm = mfma(hm.lstm);
+    for (int t = 0; t < 4; ++t)
+        for (int g = 0; g < 4; ++g)
+            for (auto& r : hm.ctx[t][g]) m->ctx[t][g].push_back(mfma(r));
+    *out = m;
+    return WV_OK;
+}
+
+extern "C" void wv_model_destroy(wv_model* m) { delete m; }
+
+// ---------------------------------------------------------------------------
+// layout and workspace
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Sub { int h, w, level, type; long long off; };
+
+int layout(const wv_config& c, int H, int W, std::vector<Sub>& out) {
+    const int J = c.levels;
+    if (H <= 0 || W <= 0) return fail(WV_ESHAPE, "empty image %dx%d", H, W);
+    if (H % (1 << J) || W % (1 << J))
+        return fail(WV_ESHAPE, "H=%d and W=%d must be divisible by 2^%d", H, W, J);
+    out.clear();
+    long long off = 0;
+    auto add = [&](int lev, int t) {
+        Sub s{H >> lev, W >> lev, lev, t, off};
+        off += (long long)s.h * s.w;
+        out.push_back(s);
+    };
+    add(J, 0);
+    for (int j = J; j >= 1; --j) {
+        add(j, 1);
+        add(j, 2);
+        add(j, 3);
+    }
+    return WV_OK;
+}
+
+// Float offsets of the per-call scratch regions (all 256-byte aligned).
+struct Scratch {
+    size_t X0, Xa, Xb, lbuf, hbuf, y, a1, a2;   // lifting
+    size_t act0, act1;                          // context
+    size_t total;
+};
+
+inline size_t al(size_t x) { return (x + 63) & ~(size_t)63; }
+
+Scratch scratch_layout(const wv_config& c, int N, int H, int W) {
+    const size_t HW = (size_t)H * W;
+    Scratch s{};
+    size_t o = 0;
+    // lifting (analysis and synthesis share the regions)
+    s.X0 = o; o = al(o + N * HW);                 // centred input / dequantised subbands
+    s.Xa = o; o = al(o + N * HW / 4);
+    s.Xb = o; o = al(o + N * HW / 4);
+    s.lbuf = o; o = al(o + N * HW / 2);
+    s.hbuf = o; o = al(o + N * HW / 2);
+    s.y = o; o = al(o + N * HW);
+    s.a1 = o; o = al(o + N * HW / 2 * c.lift_ch);
+    s.a2 = o; o = al(o + N * HW / 2 * c.lift_ch);
+    const size_t lift_total = o;
+    // context (reuses the same memory)
+    o = 0;
+    const size_t act = (size_t)N * (H / 2) * (W / 2) * c.ctx_ch;
+    s.act0 = o; o = al(o + act);
+    s.act1 = o; o = al(o + act);
+    s.total = (lift_total > o ? lift_total : o) * sizeof(float);
+    return s;
+}
+
+size_t state_floats(const wv_config& c, int N, int H, int W) {
+    return (size_t)N * (H / 2) * (W / 2) * c.ctx_ch;   // one of h / c at the finest level
+}
+
+}  // namespace
+
+extern "C" int wv_layout(const wv_config* cfg, int H, int W, wv_subband* out, int cap,
+                         long long* coefs) {
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    std::vector<Sub> lay;
+    rc = layout(*cfg, H, W, lay);
+    if (rc) return rc;
+    if (out) {
+        if (cap < (int)lay.size()) return fail(WV_ENOMEM, "need %zu entries", lay.size());
+        for (size_t i = 0; i < lay.size(); ++i)
+            out[i] = wv_subband{lay[i].h, lay[i].w, lay[i].level, lay[i].type, lay[i].off};
+    }
+    if (coefs) *coefs = (long long)H * W;
+    return WV_OK;
+}
+
+extern "C" long long wv_group_count(int h, int w, int step) {
+    if (h < 0 || w < 0 || step < 0 || step > 3) return -1;
+    const int gr = step >> 1, gc = step & 1;
+    return (long long)((h - gr + 1) >> 1) * ((w - gc + 1) >> 1);
+}
+
+extern "C" int wv_workspace_bytes(const wv_model* m, int N, int H, int W, size_t* state_bytes,
+                                  size_t* scratch_bytes) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    if (state_bytes) *state_bytes = 4 * state_floats(m->cfg, N, H, W) * sizeof(float);
+    if (scratch_bytes) *scratch_bytes = scratch_layout(m->cfg, N, H, W).total;
+    return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lifting
+// ---------------------------------------------------------------------------
+namespace {
+
+enum { F_PROW = 0, F_UROW = 1, F_PCOL = 2, F_UCOL = 3 };
+
+inline View vw(float* p, long long ps, int rs, int cs) { return View{p, ps, rs, cs}; }
+inline CView cvw(const float* p, long long ps, int rs, int cs) { return CView{p, ps, rs, cs}; }
+
+// out = A + sign * (predict ? z + N(z) : z/2 + N(z)) on an h x w array.
+int run_filter(const wv_model* m, int f, CView z, CView A, View out, int N, int h, int w,
+               int predict, float sign, float* a1, float* a2, hipStream_t s) {
+    HIPCHK(launch_lift_first(m->lift_first[f], z, N, h, w, a1, s));
+    float* cur = a1;
+    float* oth = a2;
+    const int C = m->cfg.lift_ch;
+    for (const MfmaLayer& L : m->lift_mid[f]) {
+        ConvArgs a{};
+        a.in = cur;
+        a.in_ps = (long long)h * w * C;
+        a.out = oth;
+        a.out_ps = (long long)h * w * C;
+        a.out_cs = C;
+        a.N = N;
+        a.h = h;
+        a.w = w;
+        a.tiles_x = (w + TILE_W - 1) / TILE_W;
+        a.tiles_y = (h + TILE_H - 1) / TILE_H;
+        HIPCHK(launch_conv(L, CONV_TANH, a, s));
+        float* t = cur;
+        cur = oth;
+        oth = t;
+    }
+    HIPCHK(launch_lift_last(m->lift_last[f], cur, z, A, out, N, h, w, predict, sign, m->cfg.lift_int, s));
+    return WV_OK;
+}
+
+}  // namespace
+
+extern "C" int wv_analyze(const wv_model* m, const uint8_t* d_x8, const float* d_xf, int N, int H,
+                          int W, float dL, float dH, void* d_scratch, int16_t* d_q, float* d_y,
+                          int* d_clip, void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if ((!d_x8 && !d_xf) || !d_scratch || !d_q) return fail(WV_EINVAL, "null pointer");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    if (!(dL > 0.f) || !(dH > 0.f)) return fail(WV_EINVAL, "quantiser steps must be > 0");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Scratch sc = scratch_layout(m->cfg, N, H, W);
+    float* base = (float*)d_scratch;
+    const long long HW = (long long)H * W;
+    const float* X = d_xf;
+    if (d_x8) {
+        HIPCHK(launch_center_u8(d_x8, base + sc.X0, N * HW, s));
+        X = base + sc.X0;
+    }
+    long long xps = HW;
+    float* y = d_y ? d_y : base + sc.y;
+    float* a1 = base + sc.a1;
+    float* a2 = base + sc.a2;
+    float* lb = base + sc.lbuf;
+    float* hb = base + sc.hbuf;
+    const int J = m->cfg.levels;
+    // coding-order index of HL_j: 1 + 3 (J - j); LH, HH follow.
+    for (int j = 1; j <= J; ++j) {
+        const int hx = H >> (j - 1), wx = W >> (j - 1);
+        const int hw2 = wx / 2;
+        const long long hps = (long long)hx * hw2;
+        // row step: h = odd - P_row(even); l = even + U_row(h)
+        rc = run_filter(m, F_PROW, cvw(X, xps, wx, 2), cvw(X + 1, xps, wx, 2), vw(hb, hps, hw2, 1), N,
+                        hx, hw2, 1, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_UROW, cvw(hb, hps, hw2, 1), cvw(X, xps, wx, 2), vw(lb, hps, hw2, 1), N, hx,
+                        hw2, 0, 1.f, a1, a2, s);
+        if (rc) return rc;
+        const int hs = hx / 2, ws = hw2;
+        const Sub& sHL = lay[1 + 3 * (J - j)];
+        const Sub& sLH = lay[2 + 3 * (J - j)];
+        const Sub& sHH = lay[3 + 3 * (J - j)];
+        float* xn = (j == J) ? y + lay[0].off : base + ((j & 1) ? sc.Xa : sc.Xb);
+        const long long xnps = (j == J) ? HW : (long long)hs * ws;
+        // column step on l: LH = l_odd - P_col(l_even); LL = l_even + U_col(LH)
+        rc = run_filter(m, F_PCOL, cvw(lb, hps, 2 * hw2, 1), cvw(lb + hw2, hps, 2 * hw2, 1),
+                        vw(y + sLH.off, HW, ws, 1), N, hs, ws, 1, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_UCOL, cvw(y + sLH.off, HW, ws, 1), cvw(lb, hps, 2 * hw2, 1),
+                        vw(xn, xnps, ws, 1), N, hs, ws, 0, 1.f, a1, a2, s);
+        if (rc) return rc;
+        // column step on h: HH = h_odd - P_col(h_even); HL = h_even + U_col(HH)
+        rc = run_filter(m, F_PCOL, cvw(hb, hps, 2 * hw2, 1), cvw(hb + hw2, hps, 2 * hw2, 1),
+                        vw(y + sHH.off, HW, ws, 1), N, hs, ws, 1, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_UCOL, cvw(y + sHH.off, HW, ws, 1), cvw(hb, hps, 2 * hw2, 1),
+                        vw(y + sHL.off, HW, ws, 1), N, hs, ws, 0, 1.f, a1, a2, s);
+        if (rc) return rc;
+        X = xn;
+        xps = xnps;
+    }
+    const long long n_ll = (long long)lay[0].h * lay[0].w;
+    HIPCHK(launch_quantize(y, d_q, N, HW, n_ll, dL, dH, m->cfg.sym_min, m->cfg.sym_max, d_clip, s));
+    return WV_OK;
+}
+
+extern "C" int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H,
+                             int W, float dL, float dH, void* d_scratch, float* d_xhat, uint8_t* d_u8,
+                             void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if ((!d_q && !d_y) || !d_scratch || !d_xhat) return fail(WV_EINVAL, "null pointer");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    if (d_q && (!(dL > 0.f) || !(dH > 0.f))) return fail(WV_EINVAL, "quantiser steps must be > 0");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Scratch sc = scratch_layout(m->cfg, N, H, W);
+    float* base = (float*)d_scratch;
+    const long long HW = (long long)H * W;
+    const float* y = d_y;
+    if (d_q) {
+        const long long n_ll = (long long)lay[0].h * lay[0].w;
+        HIPCHK(launch_dequantize(d_q, base + sc.X0, N, HW, n_ll, dL, dH, s));
+        y = base + sc.X0;
+    }
+    float* a1 = base + sc.a1;
+    float* a2 = base + sc.a2;
+    float* lb = base + sc.lbuf;
+    float* hb = base + sc.hbuf;
+    const int J = m->cfg.levels;
+    const float* X = y + lay[0].off;
+    long long xps = HW;
+    for (int j = J; j >= 1; --j) {
+        const int hs = H >> j, ws = W >> j;
+        const Sub& sHL = lay[1 + 3 * (J - j)];
+        const Sub& sLH = lay[2 + 3 * (J - j)];
+        const Sub& sHH = lay[3 + 3 * (J - j)];
+        const long long bps = (long long)(2 * hs) * ws;
+        // inverse column step on (LL, LH) -> l: even = LL - U_col(LH); odd = LH + P_col(even)
+        rc = run_filter(m, F_UCOL, cvw(y + sLH.off, HW, ws, 1), cvw(X, xps, ws, 1),
+                        vw(lb, bps, 2 * ws, 1), N, hs, ws, 0, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_PCOL, cvw(lb, bps, 2 * ws, 1), cvw(y + sLH.off, HW, ws, 1),
+                        vw(lb + ws, bps, 2 * ws, 1), N, hs, ws, 1, 1.f, a1, a2, s);
+        if (rc) return rc;
+        // inverse column step on (HL, HH) -> h
+        rc = run_filter(m, F_UCOL, cvw(y + sHH.off, HW, ws, 1), cvw(y + sHL.off, HW, ws, 1),
+                        vw(hb, bps, 2 * ws, 1), N, hs, ws, 0, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_PCOL, cvw(hb, bps, 2 * ws, 1), cvw(y + sHH.off, HW, ws, 1),
+                        vw(hb + ws, bps, 2 * ws, 1), N, hs, ws, 1, 1.f, a1, a2, s);
+        if (rc) return rc;
+        // inverse row step: even = l - U_row(h); odd = h + P_row(even)
+        const int ho = 2 * hs, wo = 2 * ws;
+        float* xo = (j == 1) ? d_xhat : base + ((j & 1) ? sc.Xa : sc.Xb);
+        const long long ops = (long long)ho * wo;
+        rc = run_filter(m, F_UROW, cvw(hb, bps, ws, 1), cvw(lb, bps, ws, 1), vw(xo, ops, wo, 2), N, ho,
+                        ws, 0, -1.f, a1, a2, s);
+        if (rc) return rc;
+        rc = run_filter(m, F_PROW, cvw(xo, ops, wo, 2), cvw(hb, bps, ws, 1), vw(xo + 1, ops, wo, 2), N,
+                        ho, ws, 1, 1.f, a1, a2, s);
+        if (rc) return rc;
+        X = xo;
+        xps = ops;
+    }
+    HIPCHK(launch_finalize(d_xhat, d_u8, N * HW, s));
+    return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context model
+// ---------------------------------------------------------------------------
+extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, int H, int W, int i,
+                                 int g, float* d_state, void* d_scratch, float* d_params,
+                                 void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (!d_q || !d_state || !d_scratch) return fail(WV_EINVAL, "null pointer");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3)
+        return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    const long long ng = wv_group_count(lay[i].h, lay[i].w, g);
+    if (ng > 0 && !d_params) return fail(WV_EINVAL, "null pointer");
+    if (ng == 0) return WV_OK;   // a 1-wide subband has no positions at this step
+    hipStream_t s = (hipStream_t)stream;
+    const int C = m->cfg.ctx_ch;
+    const long long HW = (long long)H * W;
+    const size_t SS = state_floats(m->cfg, N, H, W);
+    const Sub& S = lay[i];
+    float* hcur = d_state + (size_t)(i & 1) * 2 * SS;
+    float* ccur = hcur + SS;
+    const long long st_ps = (long long)S.h * S.w * C;
+    if (g == 0) {
+        ConvArgs a{};
+        a.N = N;
+        a.h = S.h;
+        a.w = S.w;
+        a.tiles_x = (S.w + TILE_W - 1) / TILE_W;
+        a.tiles_y = (S.h + TILE_H - 1) / TILE_H;
+        a.sym_step = 4;
+        a.h_out = hcur;
+        a.c_out = ccur;
+        a.st_ps = st_ps;
+        a.C = C;
+        if (i > 0) {
+            const Sub& P = lay[i - 1];
+            const int up = (S.h == 2 * P.h) ? 1 : 0;
+            float* hold = d_state + (size_t)((i - 1) & 1) * 2 * SS;
+            a.in = hold;
+            a.in_ps = (long long)P.h * P.w * C;
+            a.in_up = up;
+            a.sym = d_q + P.off;
+            a.sym_ps = HW;
+            a.sym_up = up;
+            a.c_prev = hold + SS;
+            a.cprev_ps = (long long)P.h * P.w * C;
+            a.cprev_up = up;
+        }
+        HIPCHK(launch_conv(m->lstm, CONV_LSTM, a, s));
+    }
+    float* base = (float*)d_scratch;
+    const Scratch sc = scratch_layout(m->cfg, N, H, W);
+    float* act[2] = {base + sc.act0, base + sc.act1};
+    const std::vector<MfmaLayer>& stack = m->ctx[S.type][g];
+    const float* in = hcur;
+    for (size_t l = 0; l < stack.size(); ++l) {
+        const bool last = l + 1 == stack.size();
+        ConvArgs a{};
+        a.in = in;
+        a.in_ps = st_ps;
+        a.N = N;
+        a.h = S.h;
+        a.w = S.w;
+        a.tiles_x = (S.w + TILE_W - 1) / TILE_W;
+        a.tiles_y = (S.h + TILE_H - 1) / TILE_H;
+        if (l == 0 && g > 0) {
+            a.sym = d_q + S.off;
+            a.sym_ps = HW;
+            a.sym_step = g;
+        }
+        if (!last) {
+            a.out = act[l & 1];
+            a.out_ps = st_ps;
+            a.out_cs = C;
+            HIPCHK(launch_conv(stack[l], CONV_RELU, a, s));
+            in = act[l & 1];
+        } else {
+            a.params = d_params;
+            a.step = g;
+            a.K = m->cfg.mix_k;
+            a.sigma_min = m->cfg.sigma_min;
+            HIPCHK(launch_conv(stack[l], CONV_HEAD, a, s));
+        }
+    }
+    return WV_OK;
+}
+
+extern "C" int wv_cdf_tables(const float* d_params, long long n, int K, int sym_min, int sym_max,
+                             int cdf_bits, uint16_t* d_cdf, void* stream) {
+    if (n < 0) return fail(WV_ESHAPE, "negative row count");
+    if (n > 0 && (!d_params || !d_cdf)) return fail(WV_EINVAL, "null pointer");
+    if (K < 1 || K > 4) return fail(WV_EUNSUPPORTED, "mix_k must be 1..4");
+    const int nsym = sym_max - sym_min + 1;
+    if (nsym < 2 || nsym > 255) return fail(WV_EUNSUPPORTED, "alphabet must have 2..255 symbols");
+    if (cdf_bits != 16) return fail(WV_EUNSUPPORTED, "cdf_bits must be 16");
+    HIPCHK(launch_cdf(d_params, n, K, sym_min, nsym, d_cdf, (hipStream_t)stream));
+    return WV_OK;
+}
+
+static int sym_io(const wv_config* cfg, int N, int H, int W, int i, int g, std::vector<Sub>& lay) {
+    int rc = check_cfg(cfg);
+    if (rc) return rc;
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    rc = layout(*cfg, H, W, lay);
+    if (rc) return rc;
+    if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3)
+        return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    return WV_OK;
+}
+
+extern "C" int wv_scatter_symbols(const wv_config* cfg, const uint8_t* d_sym, int N, int H, int W,
+                                  int i, int g, int16_t* d_q, void* stream) {
+    std::vector<Sub> lay;
+    int rc = sym_io(cfg, N, H, W, i, g, lay);
+    if (rc) return rc;
+    if (!d_q || (!d_sym && wv_group_count(lay[i].h, lay[i].w, g) > 0))
+        return fail(WV_EINVAL, "null pointer");
+    HIPCHK(launch_scatter(d_sym, d_q, N, (long long)H * W, lay[i].off, lay[i].h, lay[i].w, g,
+                          cfg->sym_min, (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" int wv_gather_symbols(const wv_config* cfg, const int16_t* d_q, int N, int H, int W,
+                                 int i, int g, uint8_t* d_sym, void* stream) {
+    std::vector<Sub> lay;
+    int rc = sym_io(cfg, N, H, W, i, g, lay);
+    if (rc) return rc;
+    if (!d_q || (!d_sym && wv_group_count(lay[i].h, lay[i].w, g) > 0))
+        return fail(WV_EINVAL, "null pointer");
+    HIPCHK(launch_gather(d_q, d_sym, N, (long long)H * W, lay[i].off, lay[i].h, lay[i].w, g,
+                         cfg->sym_min, (hipStream_t)stream));
+    return WV_OK;
+}
+
+static int thaar(float* f, int T, long long n, int inverse, void* stream) {
+    if (T < 1 || T > 32 || (T & (T - 1))) return fail(WV_ESHAPE, "T must be a power of two <= 32");
+    if (n < 0) return fail(WV_ESHAPE, "negative size");
+    if (!f && n > 0) return fail(WV_EINVAL, "null pointer");
+    HIPCHK(launch_thaar(f, nullptr, T, n, inverse, (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" int wv_temporal_haar_forward(float* f, int T, long long n, void* stream) {
+    return thaar(f, T, n, 0, stream);
+}
+extern "C" int wv_temporal_haar_inverse(float* f, int T, long long n, void* stream) {
+    return thaar(f, T, n, 1, stream);
+}

@@ -1,0 +1,297 @@
+// 3x3 convolution as an implicit GEMM on the gfx950 matrix cores (FP32).
+//
+// Used by every dense contraction of the path: the ConvLSTM gate conv and
+// the coding-step stacks of the context model (Sec. 3.2), and the C -> C
+// layers of the lifting filters (Sec. 3.1).
+//
+// GEMM view: M = output positions, N = output channels, K = 9 taps x Cin.
+// One workgroup (256 threads, 4 waves) owns an 8 x 16 position tile and
+// 16*NB output channels.  The (8+2) x (16+2) input halo of all Cin channels
+// is staged once in LDS (NHWC, row stride Cin+4 floats); each wave computes
+// two rows of 16 positions x NB blocks of 16 channels with
+// v_mfma_f32_16x16x4f32, A fragments read from LDS as float4 (4 channels of
+// one position per lane), B fragments read as float4 from the repacked
+// weights (L2-resident, identical for every workgroup).  The optional
+// symbol channel (int16 symbols, masked by coding step) is a separate
+// rank-9 update of three K=4 chunks.  Accumulation order is fixed, so a
+// position's result does not depend on the tile, the grid or the batch.
+#include "wv_internal.h"
+
+namespace wv {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int HALO_H = TILE_H + 2;
+constexpr int HALO_W = TILE_W + 2;
+constexpr int HALO = HALO_H * HALO_W;
+
+__device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
+
+template <int CIN, int NB, bool SYM, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
+    constexpr int STRIDE = CIN + 4;
+    constexpr int CB = CIN / 16;
+    __shared__ __attribute__((aligned(16))) float lds_in[HALO * STRIDE];
+    __shared__ float lds_s[SYM ? HALO : 1];
+    __shared__ float lds_head[MODE == CONV_HEAD ? TILE_H * TILE_W * 17 : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int t = blockIdx.x;
+    const int tx = t % a.tiles_x;
+    t /= a.tiles_x;
+    const int ty = t % a.tiles_y;
+    const int n = t / a.tiles_y;
+    const int r0 = ty * TILE_H;
+    const int c0 = tx * TILE_W;
+    const int nblk0 = blockIdx.y * NB;
+
+    // ---- stage the input halo (zero outside the plane) ----
+    {
+        const int hin = a.h >> a.in_up;
+        const int win = a.w >> a.in_up;
+        (void)hin;
+        const float* inp = a.in ? a.in + (long long)n * a.in_ps : nullptr;
+        for (int idx = tid; idx < HALO * (CIN / 4); idx += 256) {
+            const int pos = idx / (CIN / 4);
+            const int c4 = idx - pos * (CIN / 4);
+            const int hy = pos / HALO_W;
+            const int hx = pos - hy * HALO_W;
+            const int r = r0 + hy - 1;
+            const int c = c0 + hx - 1;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (inp && r >= 0 && r < a.h && c >= 0 && c < a.w) {
+                const long long off =
+                    ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c4 * 4;
+                v = *reinterpret_cast<const float4*>(inp + off);
+            }
+            *reinterpret_cast<float4*>(lds_in + pos * STRIDE + c4 * 4) = v;
+        }
+        if (SYM) {
+            const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
+            const int ws = a.w >> a.sym_up;
+            for (int pos = tid; pos < HALO; pos += 256) {
+                const int hy = pos / HALO_W;
+                const int hx = pos - hy * HALO_W;
+                const int r = r0 + hy - 1;
+                const int c = c0 + hx - 1;
+                float v = 0.f;
+                if (sp && r >= 0 && r < a.h && c >= 0 && c < a.w &&
+                    (2 * (r & 1) + (c & 1)) < a.sym_step)
+                    v = (float)sp[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
+                lds_s[pos] = v;
+            }
+        }
+    }
+    __syncthreads();
+
+    floatx4 acc[2][NB];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int m = lane & 15;
+    const int kk = lane >> 4;
+    const float* wl = L.w + (long long)lane * 4;
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3;
+        const int dx = tap - dy * 3;
+        const float* arow0 = lds_in + ((wave * 2 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            float4 av[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+                av[mb] = *reinterpret_cast<const float4*>(arow0 + mb * HALO_W * STRIDE + cb * 16);
+            float4 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                bv[nb] = *reinterpret_cast<const float4*>(
+                    wl + ((long long)(tap * CB + cb) * L.nbt + nblk0 + nb) * 256);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].x, bv[nb].x,
+                                                                       acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].y, bv[nb].y,
+                                                                       acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].z, bv[nb].z,
+                                                                       acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].w, bv[nb].w,
+                                                                       acc[mb][nb], 0, 0, 0);
+                }
+        }
+    }
+    if (SYM) {
+#pragma unroll
+        for (int chunk = 0; chunk < 3; ++chunk) {
+            const int tap = chunk * 4 + kk;
+            const int dy = tap / 3;
+            const int dx = tap - dy * 3;
+            float av[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+                av[mb] = tap < 9 ? lds_s[(wave * 2 + mb + dy) * HALO_W + m + dx] : 0.f;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float bv = L.wsym[((long long)chunk * L.nbt + nblk0 + nb) * 64 + lane];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+                    acc[mb][nb] =
+                        __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv, acc[mb][nb], 0, 0, 0);
+            }
+        }
+    }
+
+    // ---- epilogues.  Lane holds D[4*(lane/16) + i][lane % 16] of each block. ----
+    const int col = lane & 15;
+    const int rowq = (lane >> 4) * 4;
+    if (MODE == CONV_RELU || MODE == CONV_TANH) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int r = r0 + wave * 2 + mb;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int ch = (nblk0 + nb) * 16 + col;
+                const float b = L.bias[ch];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = c0 + rowq + i;
+                    if (r < a.h && c < a.w && ch < L.cout) {
+                        float v = acc[mb][nb][i] + b;
+                        v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
+                        a.out[(long long)n * a.out_ps + ((long long)r * a.w + c) * a.out_cs + ch] = v;
+                    }
+                }
+            }
+        }
+    } else if (MODE == CONV_LSTM) {
+        // Block nb of this workgroup is gate nb (input, forget, cell, output)
+        // of channels 16*blockIdx.y .. +15 (the packer orders the columns so).
+        const int ch = blockIdx.y * 16 + col;
+        const float bi = L.bias[(nblk0 + 0) * 16 + col];
+        const float bf = L.bias[(nblk0 + 1) * 16 + col];
+        const float bg = L.bias[(nblk0 + 2) * 16 + col];
+        const float bo = L.bias[(nblk0 + 3) * 16 + col];
+        const int wp = a.w >> a.cprev_up;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int r = r0 + wave * 2 + mb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = c0 + rowq + i;
+                if (r < a.h && c < a.w) {
+                    float cp = 0.f;
+                    if (a.c_prev)
+                        cp = a.c_prev[(long long)n * a.cprev_ps +
+                                      ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C +
+                                      ch];
+                    const float gi = sigmoidf_(acc[mb][0][i] + bi);
+                    const float gf = sigmoidf_(acc[mb][1][i] + bf);
+                    const float gg = tanhf(acc[mb][2][i] + bg);
+                    const float go = sigmoidf_(acc[mb][3][i] + bo);
+                    const float cn = gf * cp + gi * gg;
+                    const float hn = go * tanhf(cn);
+                    const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
+                    a.c_out[o] = cn;
+                    a.h_out[o] = hn;
+                }
+            }
+        }
+    } else {  // CONV_HEAD: raw 3K outputs of every tile position -> LDS -> step-g positions
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                lds_head[((wave * 2 + mb) * TILE_W + rowq + i) * 17 + col] =
+                    acc[mb][0][i] + L.bias[col];
+        __syncthreads();
+        if (tid < TILE_H * TILE_W) {
+            const int r = r0 + tid / TILE_W;
+            const int c = c0 + tid % TILE_W;
+            const int gr = a.step >> 1, gc = a.step & 1;
+            if (r < a.h && c < a.w && (r & 1) == gr && (c & 1) == gc) {
+                const float* v = lds_head + tid * 17;
+                const int K = a.K;
+                const int wg = (a.w - gc + 1) >> 1;
+                const int hg = (a.h - gr + 1) >> 1;
+                const long long gi = (long long)(r >> 1) * wg + (c >> 1);
+                float* o = a.params + ((long long)n * hg * wg + gi) * 3 * K;
+                float mx = v[0];
+                for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
+                float e[4];
+                float se = 0.f;
+                for (int k = 0; k < K; ++k) {
+                    e[k] = __expf(v[k] - mx);
+                    se += e[k];
+                }
+                for (int k = 0; k < K; ++k) o[k] = e[k] / se;
+                for (int k = 0; k < K; ++k) o[K + k] = v[K + k];
+                for (int k = 0; k < K; ++k) {
+                    const float x = v[2 * K + k];
+                    const float sp = log1pf(__expf(-fabsf(x))) + fmaxf(x, 0.f);
+                    o[2 * K + k] = fmaxf(sp, a.sigma_min);
+                }
+            }
+        }
+    }
+}
+
+template <int CIN, int NB, bool SYM, int MODE>
+hipError_t launch_t(const MfmaLayer& L, const ConvArgs& a, hipStream_t s) {
+    const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
+    dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
+    hipLaunchKernelGGL((conv3x3_mfma_f32<CIN, NB, SYM, MODE>), grid, dim3(256), 0, s, L, a);
+    return hipGetLastError();
+}
+
+template <int CIN, int NB, bool SYM>
+hipError_t dispatch_mode(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+    switch (mode) {
+        case CONV_RELU: return launch_t<CIN, NB, SYM, CONV_RELU>(L, a, s);
+        case CONV_TANH: return launch_t<CIN, NB, SYM, CONV_TANH>(L, a, s);
+        case CONV_LSTM: return NB == 4 ? launch_t<CIN, 4, SYM, CONV_LSTM>(L, a, s) : hipErrorInvalidValue;
+        case CONV_HEAD: return NB == 1 ? launch_t<CIN, 1, SYM, CONV_HEAD>(L, a, s) : hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int CIN, int NB>
+hipError_t dispatch_sym(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+    return L.has_sym ? dispatch_mode<CIN, NB, true>(L, mode, a, s)
+                     : dispatch_mode<CIN, NB, false>(L, mode, a, s);
+}
+
+template <int CIN>
+hipError_t dispatch_nb(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+    int nb = (mode == CONV_HEAD) ? 1 : (L.nbt >= 4 ? 4 : L.nbt);
+    if (mode == CONV_LSTM) nb = 4;
+    switch (nb) {
+        case 1: return dispatch_sym<CIN, 1>(L, mode, a, s);
+        case 2: return dispatch_sym<CIN, 2>(L, mode, a, s);
+        case 4: return dispatch_sym<CIN, 4>(L, mode, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+    if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;
+    if (mode != CONV_HEAD && mode != CONV_LSTM && (L.nbt % (L.nbt >= 4 ? 4 : L.nbt)) != 0)
+        return hipErrorInvalidValue;
+    if (mode == CONV_LSTM && L.nbt % 4 != 0) return hipErrorInvalidValue;
+    switch (L.cin) {
+        case 16: return dispatch_nb<16>(L, mode, a, s);
+        case 32: return dispatch_nb<32>(L, mode, a, s);
+        case 64: return dispatch_nb<64>(L, mode, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wv

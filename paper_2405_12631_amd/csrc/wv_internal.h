@@ -1,0 +1,110 @@
+// Internal declarations shared by the C ABI (wv_api.hip) and the kernels
+// (wv_conv.hip, wv_lift.hip, wv_cdf.hip, wv_misc.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wv.h"
+
+namespace wv {
+
+// Strided 2-D view of a stack of planes: element (n, r, c) lives at
+// p[n * ps + r * rs + c * cs].  Used to read even/odd samples of a plane
+// and to write subbands straight into the packed layout without copies.
+struct View {
+    float* p;
+    long long ps;
+    int rs, cs;
+};
+struct CView {
+    const float* p;
+    long long ps;
+    int rs, cs;
+};
+inline CView cview(View v) { return CView{v.p, v.ps, v.rs, v.cs}; }
+
+// Output tile of one conv workgroup: TILE_H x TILE_W positions, 4 waves, each
+// wave two rows of 16 positions.
+constexpr int TILE_H = 8;
+constexpr int TILE_W = 16;
+
+// Epilogue of the MFMA conv kernel.
+enum ConvMode { CONV_RELU = 0, CONV_TANH = 1, CONV_LSTM = 2, CONV_HEAD = 3 };
+
+// One conv3x3 layer repacked for the MFMA kernel (see pack_mfma_layer):
+//   w    : [9][cin/16][nbt][64 lanes][4]  float B fragments
+//   wsym : [3][nbt][64 lanes]             symbol-channel B fragments or null
+//   bias : [nbt * 16]
+struct MfmaLayer {
+    const float* w;
+    const float* wsym;
+    const float* bias;
+    int cin;       // float input channels (multiple of 16)
+    int cout;      // real output channels
+    int nbt;       // output blocks of 16 (padded)
+    int has_sym;   // 1: extra input channel 0 read from int16 symbols
+};
+
+// A 1 -> C or C -> 1 lifting conv for the vector kernels: w [9][C], bias [C] / [1].
+struct VecLayer {
+    const float* w;
+    const float* bias;
+    int ch;
+};
+
+struct ConvArgs {
+    const float* in;       // NHWC float input [N][h >> in_up][w >> in_up][cin], or null (zeros)
+    long long in_ps;       // plane stride (floats)
+    int in_up;             // 1: nearest x2 upsampling on read
+    const int16_t* sym;    // symbol channel base (plane 0 of this subband) or null (zeros)
+    long long sym_ps;      // plane stride of the packed symbols
+    int sym_up;            // 1: symbol plane at half resolution (nearest x2)
+    int sym_step;          // positions with group >= sym_step read as zero
+    float* out;            // NHWC output [N][h][w][out_cs]
+    long long out_ps;
+    int out_cs;
+    int N, h, w, tiles_x, tiles_y;
+    // CONV_LSTM
+    const float* c_prev;   // NHWC [N][h >> cprev_up][w >> cprev_up][C] or null (zeros)
+    long long cprev_ps;
+    int cprev_up;
+    float* h_out;          // NHWC [N][h][w][C]
+    float* c_out;
+    long long st_ps;
+    int C;
+    // CONV_HEAD
+    float* params;         // [N][n_g][3K]
+    int step, K;
+    float sigma_min;
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s);
+
+// Lifting filter pieces.
+//   first: a1[n][r][c][ch] = tanh(b[ch] + sum_tap w[tap][ch] z(n, r+dy-1, c+dx-1))
+//   last : v = b + sum_tap,ch w[tap][ch] a2[n][r+dy-1][c+dx-1][ch];
+//          f = (predict ? z + v : z/2 + v), rounded if lift_int;
+//          out(n, r, c) = A(n, r, c) + sign * f
+hipError_t launch_lift_first(const VecLayer& L, CView z, int N, int h, int w, float* a1,
+                             hipStream_t s);
+hipError_t launch_lift_last(const VecLayer& L, const float* a2, CView z, CView A, View out,
+                            int N, int h, int w, int predict, float sign, int lift_int,
+                            hipStream_t s);
+
+hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s);
+hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
+                           float dL, float dH, int smin, int smax, int* clip, hipStream_t s);
+hipError_t launch_dequantize(const int16_t* q, float* y, int N, long long per_plane,
+                             long long n_ll, float dL, float dH, hipStream_t s);
+hipError_t launch_finalize(float* x, uint8_t* u8, long long n, hipStream_t s);
+hipError_t launch_scatter(const uint8_t* sym, int16_t* q, int N, long long q_ps, long long off,
+                          int h, int w, int step, int smin, hipStream_t s);
+hipError_t launch_gather(const int16_t* q, uint8_t* sym, int N, long long q_ps, long long off,
+                         int h, int w, int step, int smin, hipStream_t s);
+hipError_t launch_cdf(const float* params, long long n, int K, int smin, int nsym,
+                      uint16_t* cdf, hipStream_t s);
+hipError_t launch_thaar(float* f, float* tmp, int T, long long n, int inverse, hipStream_t s);
+
+}  // namespace wv

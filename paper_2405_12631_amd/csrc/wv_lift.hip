@@ -1,0 +1,281 @@
+// Lifting filter end layers and elementwise kernels.
+//
+// A predict/update filter (Sec. 3.1) is conv(1 -> C), tanh, conv(C -> C),
+// tanh, ..., conv(C -> 1).  The C -> C layers run on the MFMA conv kernel;
+// the two end layers are thin (one input or one output channel) and run
+// here on the vector ALUs, one thread per position.  The last layer also
+// applies the lifting update in place of a separate pass:
+//   predict: f = z + N(z); update: f = z/2 + N(z); optionally rounded;
+//   out = A + sign * f.
+#include "wv_internal.h"
+
+namespace wv {
+namespace {
+
+constexpr int BLK = 256;
+
+inline unsigned nblocks(long long n) { return (unsigned)((n + BLK - 1) / BLK); }
+
+template <int C>
+__global__ __launch_bounds__(BLK) void lift_first_k(const VecLayer L, const CView z, int N, int h,
+                                                   int w, float* __restrict__ a1) {
+    const long long idx = (long long)blockIdx.x * BLK + threadIdx.x;
+    const long long total = (long long)N * h * w;
+    if (idx >= total) return;
+    const int c = (int)(idx % w);
+    const long long t = idx / w;
+    const int r = (int)(t % h);
+    const int n = (int)(t / h);
+    const float* zp = z.p + (long long)n * z.ps;
+    float zv[9];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int rr = r + tap / 3 - 1;
+        const int cc = c + tap % 3 - 1;
+        zv[tap] = (rr >= 0 && rr < h && cc >= 0 && cc < w) ? zp[(long long)rr * z.rs + (long long)cc * z.cs]
+                                                           : 0.f;
+    }
+    float* o = a1 + idx * C;
+#pragma unroll
+    for (int ch = 0; ch < C; ch += 4) {
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float s = L.bias[ch + j];
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) s = fmaf(L.w[tap * C + ch + j], zv[tap], s);
+            v[j] = tanhf(s);
+        }
+        *reinterpret_cast<float4*>(o + ch) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+}
+
+template <int C>
+__global__ __launch_bounds__(BLK) void lift_last_k(const VecLayer L, const float* __restrict__ a2,
+                                                  const CView z, const CView A, const View out,
+                                                  int N, int h, int w, int predict, float sign,
+                                                  int lift_int) {
+    const long long idx = (long long)blockIdx.x * BLK + threadIdx.x;
+    const long long total = (long long)N * h * w;
+    if (idx >= total) return;
+    const int c = (int)(idx % w);
+    const long long t = idx / w;
+    const int r = (int)(t % h);
+    const int n = (int)(t / h);
+    float s = L.bias[0];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int rr = r + tap / 3 - 1;
+        const int cc = c + tap % 3 - 1;
+        if (rr < 0 || rr >= h || cc < 0 || cc >= w) continue;
+        const float4* p = reinterpret_cast<const float4*>(a2 + (((long long)n * h + rr) * w + cc) * C);
+        const float* wt = L.w + tap * C;
+#pragma unroll
+        for (int j = 0; j < C / 4; ++j) {
+            const float4 v = p[j];
+            s = fmaf(wt[4 * j + 0], v.x, s);
+            s = fmaf(wt[4 * j + 1], v.y, s);
+            s = fmaf(wt[4 * j + 2], v.z, s);
+            s = fmaf(wt[4 * j + 3], v.w, s);
+        }
+    }
+    const float zz = z.p[(long long)n * z.ps + (long long)r * z.rs + (long long)c * z.cs];
+    float f = predict ? zz + s : 0.5f * zz + s;
+    if (lift_int) f = rintf(f);
+    const float av = A.p[(long long)n * A.ps + (long long)r * A.rs + (long long)c * A.cs];
+    out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = av + sign * f;
+}
+
+__global__ __launch_bounds__(BLK) void center_u8_k(const uint8_t* __restrict__ x8,
+                                                  float* __restrict__ xf, long long n) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) xf[i] = (float)x8[i] - 128.0f;
+}
+
+__global__ __launch_bounds__(BLK) void quantize_k(const float* __restrict__ y, int16_t* __restrict__ q,
+                                                 long long total, long long per_plane, long long n_ll,
+                                                 float dL, float dH, int smin, int smax, int* clip) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    if (i >= total) return;
+    const float d = (i % per_plane) < n_ll ? dL : dH;
+    const float v = rintf(y[i] * d);
+    const bool out = v < (float)smin || v > (float)smax;
+    q[i] = (int16_t)fminf(fmaxf(v, (float)smin), (float)smax);
+    if (clip) {
+        const unsigned long long m = __ballot(out);
+        if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(clip, __popcll(m));
+    }
+}
+
+__global__ __launch_bounds__(BLK) void dequantize_k(const int16_t* __restrict__ q, float* __restrict__ y,
+                                                   long long total, long long per_plane, long long n_ll,
+                                                   float dL, float dH) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    if (i >= total) return;
+    const float d = (i % per_plane) < n_ll ? dL : dH;
+    y[i] = (float)q[i] / d;
+}
+
+__global__ __launch_bounds__(BLK) void finalize_k(float* __restrict__ x, uint8_t* __restrict__ u8,
+                                                 long long n) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    if (i >= n) return;
+    const float v = x[i] + 128.0f;
+    x[i] = v;
+    if (u8) u8[i] = (uint8_t)fminf(fmaxf(rintf(v), 0.f), 255.f);
+}
+
+// Step-g lattice of an h x w subband: row-major (r', c') with r = 2r' + g/2, c = 2c' + g%2.
+__global__ __launch_bounds__(BLK) void scatter_k(const uint8_t* __restrict__ sym, int16_t* __restrict__ q,
+                                                int N, long long q_ps, long long off, int h, int w,
+                                                int gr, int gc, int hg, int wg, int smin) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    const long long ng = (long long)hg * wg;
+    if (i >= (long long)N * ng) return;
+    const int n = (int)(i / ng);
+    const long long gi = i - (long long)n * ng;
+    const int r = 2 * (int)(gi / wg) + gr;
+    const int c = 2 * (int)(gi % wg) + gc;
+    q[(long long)n * q_ps + off + (long long)r * w + c] = (int16_t)((int)sym[i] + smin);
+}
+
+__global__ __launch_bounds__(BLK) void gather_k(const int16_t* __restrict__ q, uint8_t* __restrict__ sym,
+                                               int N, long long q_ps, long long off, int h, int w,
+                                               int gr, int gc, int hg, int wg, int smin) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    const long long ng = (long long)hg * wg;
+    if (i >= (long long)N * ng) return;
+    const int n = (int)(i / ng);
+    const long long gi = i - (long long)n * ng;
+    const int r = 2 * (int)(gi / wg) + gr;
+    const int c = 2 * (int)(gi % wg) + gc;
+    sym[i] = (uint8_t)((int)q[(long long)n * q_ps + off + (long long)r * w + c] - smin);
+}
+
+// Temporal Haar lifting of T <= 32 frames; one thread owns one sample of every frame.
+__global__ __launch_bounds__(BLK) void thaar_k(float* __restrict__ f, int T, long long n, int inverse) {
+    const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
+    if (i >= n) return;
+    float v[32], o[32];
+    for (int t = 0; t < T; ++t) v[t] = f[(long long)t * n + i];
+    if (!inverse) {
+        // v holds the current low frames (m of them) at v[0..m); highs land at o[m/2..m).
+        int m = T;
+        while (m > 1) {
+            const int hm = m / 2;
+            for (int k = 0; k < hm; ++k) {
+                const float hh = v[2 * k + 1] - v[2 * k];
+                o[hm + k] = hh;
+                v[k] = v[2 * k] + 0.5f * hh;
+            }
+            m = hm;
+        }
+        o[0] = v[0];
+    } else {
+        // Subbands [L_J, H_J, H_{J-1} (2), ..., H_1 (T/2)] -> frames.
+        float cur[32];
+        cur[0] = v[0];
+        int m = 1;
+        while (m < T) {
+            for (int k = 0; k < m; ++k) {
+                const float hh = v[m + k];
+                const float e = cur[k] - 0.5f * hh;
+                o[2 * k] = e;
+                o[2 * k + 1] = hh + e;
+            }
+            m *= 2;
+            for (int k = 0; k < m; ++k) cur[k] = o[k];
+        }
+    }
+    for (int t = 0; t < T; ++t) f[(long long)t * n + i] = o[t];
+}
+
+}  // namespace
+
+hipError_t launch_lift_first(const VecLayer& L, CView z, int N, int h, int w, float* a1,
+                             hipStream_t s) {
+    const long long n = (long long)N * h * w;
+    if (n == 0) return hipSuccess;
+    if (L.ch == 16)
+        hipLaunchKernelGGL(lift_first_k<16>, dim3(nblocks(n)), dim3(BLK), 0, s, L, z, N, h, w, a1);
+    else if (L.ch == 32)
+        hipLaunchKernelGGL(lift_first_k<32>, dim3(nblocks(n)), dim3(BLK), 0, s, L, z, N, h, w, a1);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_lift_last(const VecLayer& L, const float* a2, CView z, CView A, View out, int N,
+                            int h, int w, int predict, float sign, int lift_int, hipStream_t s) {
+    const long long n = (long long)N * h * w;
+    if (n == 0) return hipSuccess;
+    if (L.ch == 16)
+        hipLaunchKernelGGL(lift_last_k<16>, dim3(nblocks(n)), dim3(BLK), 0, s, L, a2, z, A, out, N, h,
+                           w, predict, sign, lift_int);
+    else if (L.ch == 32)
+        hipLaunchKernelGGL(lift_last_k<32>, dim3(nblocks(n)), dim3(BLK), 0, s, L, a2, z, A, out, N, h,
+                           w, predict, sign, lift_int);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(center_u8_k, dim3(nblocks(n)), dim3(BLK), 0, s, x8, xf, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
+                           float dL, float dH, int smin, int smax, int* clip, hipStream_t s) {
+    const long long n = (long long)N * per_plane;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(quantize_k, dim3(nblocks(n)), dim3(BLK), 0, s, y, q, n, per_plane, n_ll, dL,
+                       dH, smin, smax, clip);
+    return hipGetLastError();
+}
+
+hipError_t launch_dequantize(const int16_t* q, float* y, int N, long long per_plane, long long n_ll,
+                             float dL, float dH, hipStream_t s) {
+    const long long n = (long long)N * per_plane;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(dequantize_k, dim3(nblocks(n)), dim3(BLK), 0, s, q, y, n, per_plane, n_ll, dL,
+                       dH);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(float* x, uint8_t* u8, long long n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_k, dim3(nblocks(n)), dim3(BLK), 0, s, x, u8, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint8_t* sym, int16_t* q, int N, long long q_ps, long long off, int h,
+                          int w, int step, int smin, hipStream_t s) {
+    const int gr = step >> 1, gc = step & 1;
+    const int hg = (h - gr + 1) >> 1, wg = (w - gc + 1) >> 1;
+    const long long n = (long long)N * hg * wg;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_k, dim3(nblocks(n)), dim3(BLK), 0, s, sym, q, N, q_ps, off, h, w, gr,
+                       gc, hg, wg, smin);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const int16_t* q, uint8_t* sym, int N, long long q_ps, long long off, int h,
+                         int w, int step, int smin, hipStream_t s) {
+    const int gr = step >> 1, gc = step & 1;
+    const int hg = (h - gr + 1) >> 1, wg = (w - gc + 1) >> 1;
+    const long long n = (long long)N * hg * wg;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_k, dim3(nblocks(n)), dim3(BLK), 0, s, q, sym, N, q_ps, off, h, w, gr, gc,
+                       hg, wg, smin);
+    return hipGetLastError();
+}
+
+hipError_t launch_thaar(float* f, float* /*tmp*/, int T, long long n, int inverse, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (T < 1 || T > 32 || (T & (T - 1))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(thaar_k, dim3(nblocks(n)), dim3(BLK), 0, s, f, T, n, inverse);
+    return hipGetLastError();
+}
+
+}  // namespace wv

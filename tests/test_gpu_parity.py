@@ -1,0 +1,250 @@
+"""HIP path vs the FP64 oracle on identical seeded inputs (needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from wvgen import get_config, gradient_noise_image, sinusoid_1f_planes
+from gpu_common import (PARAM_RTOL, XHAT_ATOL, check_cdf_rows, model_for, need_gpu, param_err,
+                        q_to_device, say)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small():
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    cfg = get_config("gray64")
+    model, w = model_for(cfg)
+    x = gradient_noise_image(64, 64, seed=1)[None]
+    ys = O.analyze(x, cfg, w)
+    qs, _ = O.quantize(ys, cfg)
+    ws = codec.Workspace(model, 1, 64, 64)
+    return dict(cfg=cfg, model=model, w=w, x=x, ys=ys, qs=qs, ws=ws, codec=codec)
+
+
+def test_analyze_matches_oracle(small):
+    say("analyze gray64")
+    c = small["codec"]
+    q, y, clip = c.analyze(small["model"], torch.from_numpy(small["x"]).cuda(), small["ws"], want_y=True)
+    y_ref = O.pack(small["ys"])
+    y_gpu = y.cpu().numpy()
+    assert np.max(np.abs(y_gpu - y_ref)) < 2e-3
+    q_ref = O.pack(small["qs"])
+    q_gpu = q.cpu().numpy().astype(np.int64)
+    bad = np.nonzero(q_gpu != q_ref)
+    d = 1.0 / small["cfg"]["step"]
+    assert np.all(np.abs(q_gpu[bad] - q_ref[bad]) == 1)
+    assert np.all(np.abs(np.abs(y_ref[bad] * d - np.floor(y_ref[bad] * d)) - 0.5) < 1e-3)
+    assert int(clip.item()) == O.quantize(small["ys"], small["cfg"])[1]
+
+
+def test_synthesize_matches_oracle(small):
+    say("synthesize gray64")
+    c = small["codec"]
+    xh, u8 = c.synthesize(small["model"], small["ws"], q=q_to_device(small["qs"]), want_u8=True)
+    ref = O.synthesize(O.dequantize(small["qs"], small["cfg"]), small["cfg"], small["w"])
+    assert np.max(np.abs(xh.cpu().numpy() - ref)) <= XHAT_ATOL
+    assert np.array_equal(u8.cpu().numpy(), np.clip(np.rint(xh.cpu().numpy()), 0, 255).astype(np.uint8))
+
+
+def test_context_params_match_oracle_every_step(small):
+    say("context params gray64")
+    c = small["codec"]
+    cfg = small["cfg"]
+    got = c.params_all(small["model"], q_to_device(small["qs"]), small["ws"])
+    ref = O.context_params_all(small["qs"], cfg, small["w"])
+    worst = 0.0
+    for i in range(len(ref)):
+        for g in range(4):
+            e = param_err(got[i][g].cpu().numpy(), ref[i][g], cfg["mix_k"])
+            worst = max(worst, e)
+            assert e <= PARAM_RTOL, (i, g, e)
+    say("worst param rel err", worst)
+
+
+def test_cdf_tables_match_oracle_and_invariants(small):
+    say("cdf gray64")
+    c = small["codec"]
+    model, cfg = small["model"], small["cfg"]
+    got = c.params_all(model, q_to_device(small["qs"]), small["ws"])
+    for i in (0, 3, 6):
+        for g in range(4):
+            cdf = c.cdf_tables(model, got[i][g])
+            check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[i][g].cpu().numpy(), cfg)
+
+
+def test_cdf_extreme_params():
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    cfg = get_config("gray64")
+    model, _ = model_for(cfg)
+    rng = np.random.default_rng(41)
+    n = 5000
+    logits = rng.normal(0, 4, (n, 3))
+    w = np.exp(logits - logits.max(1, keepdims=True))
+    w /= w.sum(1, keepdims=True)
+    mu = rng.uniform(-90, 90, (n, 3))
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(400), (n, 3)))
+    prm = torch.from_numpy(np.concatenate([w, mu, sg], 1).astype(np.float32)).cuda()
+    for m in (1, 63, 64, 65, 1000, n):       # ragged last workgroup of rows
+        say("cdf rows", m)
+        cdf = codec.cdf_tables(model, prm[:m])
+        check_cdf_rows(cdf.cpu().numpy().view(np.uint16), prm[:m].cpu().numpy(), cfg)
+    empty = codec.cdf_tables(model, prm[:0])
+    assert empty.shape[0] == 0
+
+
+def test_encode_decode_roundtrip_bit_exact(small):
+    say("roundtrip gray64")
+    c = small["codec"]
+    model = small["model"]
+    data, q_enc = c.encode(model, small["x"])
+    xh, u8, q_dec = c.decode(model, data)
+    assert torch.equal(q_enc, q_dec)
+    xs, _ = c.synthesize(model, c.Workspace(model, 1, 64, 64), q=q_enc)
+    assert torch.equal(xs, xh)
+    # The bitstream is close to the ideal code length of the tables.
+    n_coef = 64 * 64
+    assert len(data) * 8 / n_coef < 8.0
+    # Corruption is reported, not crashed on.
+    bad = bytearray(data)
+    bad[-5] ^= 0xFF
+    with pytest.raises(Exception):
+        c.decode(model, bytes(bad))
+
+
+def test_decode_elided_deterministic_and_matches_synthesis(small):
+    say("elided decode determinism")
+    c = small["codec"]
+    model, ws = small["model"], small["ws"]
+    qk = q_to_device(small["qs"])
+    syms = c.prepare_elided(model, qk, ws)
+    outs = []
+    for _ in range(2):
+        q = torch.zeros_like(qk)
+        outs.append((c.decode_elided(model, syms, ws, q).clone(), q.clone(), ws.cdf.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][2], outs[1][2])
+    assert torch.equal(outs[0][1], qk)
+
+
+@pytest.mark.parametrize("H,W,J", [(36, 52, 2), (48, 80, 4), (16, 16, 4)])
+def test_ragged_and_odd_subbands(H, W, J):
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("ragged", H, W, J)
+    cfg = get_config("gray64", levels=J)
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(H, W, planes=2, seed=7)
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    ws = codec.Workspace(model, 2, H, W)
+    got = codec.params_all(model, q_to_device(qs), ws)
+    ref = O.context_params_all(qs, cfg, w)
+    for i in range(len(ref)):
+        for g in range(4):
+            assert param_err(got[i][g].cpu().numpy(), ref[i][g], 3) <= PARAM_RTOL, (i, g)
+    xh, _ = codec.synthesize(model, ws, q=q_to_device(qs))
+    assert np.max(np.abs(xh.cpu().numpy() - O.synthesize(O.dequantize(qs, cfg), cfg, w))) <= XHAT_ATOL
+
+
+def test_large_model_small_image_parity():
+    """The 64-channel, 4-layer context model and 32-channel lifting on a 64x96 3-plane image."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("ycbcr model 64x96")
+    cfg = get_config("ycbcr512x768")
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=2)
+    ys = O.analyze(x, cfg, w)
+    qs, _ = O.quantize(ys, cfg)
+    ws = codec.Workspace(model, 3, 64, 96)
+    q, y, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws, want_y=True)
+    assert np.max(np.abs(y.cpu().numpy() - O.pack(ys))) < 5e-3
+    got = codec.params_all(model, q_to_device(qs), ws)
+    ref = O.context_params_all(qs, cfg, w)
+    worst = max(param_err(got[i][g].cpu().numpy(), ref[i][g], 3) for i in range(13) for g in range(4))
+    say("worst param rel err", worst)
+    assert worst <= PARAM_RTOL
+    xh, _ = codec.synthesize(model, ws, q=q_to_device(qs))
+    assert np.max(np.abs(xh.cpu().numpy() - O.synthesize(O.dequantize(qs, cfg), cfg, w))) <= XHAT_ATOL
+
+
+def test_batch_invariance_bitwise():
+    """A plane's parameters and reconstruction do not depend on the other planes of the batch."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("batch invariance")
+    cfg = get_config("ycbcr512x768")
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=4)
+    ws3 = codec.Workspace(model, 3, 64, 96)
+    ws1 = codec.Workspace(model, 1, 64, 96)
+    q3, _, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws3)
+    q1, _, _ = codec.analyze(model, torch.from_numpy(x[1:2]).cuda(), ws1)
+    assert torch.equal(q3[1:2], q1)
+    p3 = codec.params_all(model, q3, ws3)
+    p1 = codec.params_all(model, q1, ws1)
+    for i in range(13):
+        for g in range(4):
+            assert torch.equal(p3[i][g][1:2], p1[i][g])
+    x3, _ = codec.synthesize(model, ws3, q=q3)
+    x1, _ = codec.synthesize(model, ws1, q=q1)
+    assert torch.equal(x3[1:2], x1)
+
+
+def test_integer_lifting_perfect_reconstruction_bit_exact():
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("integer lifting PR")
+    cfg = get_config("ycbcr512x768", lift_int=1)
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=5)
+    ws = codec.Workspace(model, 3, 64, 96)
+    _, y, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws, want_y=True)
+    yg = y.cpu().numpy()
+    assert np.array_equal(yg, np.rint(yg))
+    xh, u8 = codec.synthesize(model, ws, y=y, want_u8=True)
+    assert np.array_equal(xh.cpu().numpy(), x.astype(np.float32))
+    assert np.array_equal(u8.cpu().numpy(), x)
+    y_ref = O.pack(O.analyze(x, cfg, w))
+    assert np.mean(yg == y_ref) > 0.999
+
+
+def test_float_lifting_reconstruction_from_y():
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("float lifting PR")
+    cfg = get_config("ycbcr512x768")
+    model, _ = model_for(cfg)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=6)
+    ws = codec.Workspace(model, 3, 64, 96)
+    _, y, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws, want_y=True)
+    xh, _ = codec.synthesize(model, ws, y=y)
+    assert np.max(np.abs(xh.cpu().numpy() - x)) < 1e-3
+
+
+def test_temporal_haar_matches_oracle():
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("temporal haar")
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((8, 5, 7)).astype(np.float32)
+    t = torch.from_numpy(f).cuda()
+    codec.temporal_haar(t)
+    np.testing.assert_allclose(t.cpu().numpy(), O.temporal_haar_forward(f, 3), atol=1e-5)
+    codec.temporal_haar(t, inverse=True)
+    np.testing.assert_allclose(t.cpu().numpy(), f, atol=1e-5)
+
+
+def test_device_entry_points_reject_bad_calls(small):
+    from paper_2405_12631_amd import _lib as L
+    c = small["codec"]
+    ws = small["ws"]
+    q = q_to_device(small["qs"])
+    rc = L.lib().wv_context_params(small["model"].h, c._ptr(q), 1, 64, 64, 7, 0, c._ptr(ws.state),
+                                   c._ptr(ws.scratch), c._ptr(ws.params), c._stream())
+    assert rc == L.WV_EORDER
+    rc = L.lib().wv_context_params(small["model"].h, c._ptr(q), 1, 62, 64, 0, 0, c._ptr(ws.state),
+                                   c._ptr(ws.scratch), c._ptr(ws.params), c._stream())
+    assert rc == L.WV_ESHAPE
