@@ -10,8 +10,10 @@
 // is staged once in LDS (NHWC, row stride Cin+4 floats); each wave computes
 // two rows of 16 positions x NB blocks of 16 channels with
 // v_mfma_f32_16x16x4f32, A fragments read from LDS as float4 (4 channels of
-// one position per lane), B fragments read as float4 from the repacked
-// weights (L2-resident, identical for every workgroup).  The optional
+// one position per lane).  The weights of one tap (Cin x 16*NB, repacked as
+// B fragments) are staged in LDS by the whole workgroup; the next tap's
+// slice is fetched into registers while the current tap computes, so the
+// MFMA loop reads only LDS.  The optional
 // symbol channel (int16 symbols, masked by coding step) is a separate
 // rank-9 update of three K=4 chunks.  Accumulation order is fixed, so a
 // position's result does not depend on the tile, the grid or the batch.
@@ -30,11 +32,16 @@ __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __ex
 
 template <int CIN, int NB, bool SYM, int MODE>
 __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
-    constexpr int STRIDE = CIN + 4;
+    constexpr int STRIDE = CIN + 4;          // 68 floats for CIN = 64: conflict-free float4 reads
     constexpr int CB = CIN / 16;
+    constexpr int BV4 = CB * NB * 64;        // float4 of B per tap for this workgroup's N blocks
+    constexpr int BPT = (BV4 + 255) / 256;   // float4 per thread
+    constexpr int MB = (MODE == CONV_HEAD) ? 1 : 2;   // head: only the row parity its step codes
     __shared__ __attribute__((aligned(16))) float lds_in[HALO * STRIDE];
+    __shared__ __attribute__((aligned(16))) float4 lds_w[BV4];
     __shared__ float lds_s[SYM ? HALO : 1];
-    __shared__ float lds_head[MODE == CONV_HEAD ? TILE_H * TILE_W * 17 : 1];
+    __shared__ float lds_ws[SYM ? 3 * NB * 64 : 1];
+    __shared__ float lds_head[MODE == CONV_HEAD ? 4 * TILE_W * 17 : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -47,12 +54,45 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     const int r0 = ty * TILE_H;
     const int c0 = tx * TILE_W;
     const int nblk0 = blockIdx.y * NB;
+    const int row0 = wave * 2 + (MODE == CONV_HEAD ? (a.step >> 1) : 0);   // first tile row of this wave
+
+    // B fragments of one tap for blocks [nblk0, nblk0 + NB): global [tap][cb][nbt][64][4].
+    // Thread tid moves float4 number tid + 256 k (k < BPT <= 4) of the slice, whose
+    // layout in LDS is [cb][nb][64 lanes].  Named registers keep the prefetch out of memory.
+    static_assert(BPT <= 4, "B slice larger than four float4 per thread");
+    const float4* wg = reinterpret_cast<const float4*>(L.w);
+    auto boff_of = [&](int k) -> long long {
+        const int idx = (tid + k * 256) < BV4 ? tid + k * 256 : 0;
+        const int cb = idx / (NB * 64);
+        const int rem = idx - cb * (NB * 64);
+        return ((long long)cb * L.nbt + nblk0 + (rem >> 6)) * 64 + (rem & 63);
+    };
+    const long long bo0 = boff_of(0);
+    const long long bo1 = BPT > 1 ? boff_of(1) : 0;
+    const long long bo2 = BPT > 2 ? boff_of(2) : 0;
+    const long long bo3 = BPT > 3 ? boff_of(3) : 0;
+    const long long btap = (long long)CB * L.nbt * 64;   // float4 per tap of the whole layer
+    float4 b0, b1, b2, b3;
+#define WV_LOAD_B(tp)                                          \
+    {                                                          \
+        const float4* wt_ = wg + (long long)(tp) * btap;       \
+        b0 = wt_[bo0];                                         \
+        if (BPT > 1) b1 = wt_[bo1];                            \
+        if (BPT > 2) b2 = wt_[bo2];                            \
+        if (BPT > 3) b3 = wt_[bo3];                            \
+    }
+#define WV_STORE_B()                                                       \
+    {                                                                      \
+        if (BV4 >= 256 || tid < BV4) lds_w[tid] = b0;                      \
+        if (BPT > 1 && (BV4 >= 512 || tid + 256 < BV4)) lds_w[tid + 256] = b1; \
+        if (BPT > 2 && (BV4 >= 768 || tid + 512 < BV4)) lds_w[tid + 512] = b2; \
+        if (BPT > 3 && (BV4 >= 1024 || tid + 768 < BV4)) lds_w[tid + 768] = b3; \
+    }
+    WV_LOAD_B(0)
 
     // ---- stage the input halo (zero outside the plane) ----
     {
-        const int hin = a.h >> a.in_up;
         const int win = a.w >> a.in_up;
-        (void)hin;
         const float* inp = a.in ? a.in + (long long)n * a.in_ps : nullptr;
         for (int idx = tid; idx < HALO * (CIN / 4); idx += 256) {
             const int pos = idx / (CIN / 4);
@@ -83,37 +123,43 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                     v = (float)sp[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
                 lds_s[pos] = v;
             }
+            for (int idx = tid; idx < 3 * NB * 64; idx += 256) {
+                const int chunk = idx / (NB * 64);
+                const int rem = idx - chunk * (NB * 64);
+                lds_ws[idx] = L.wsym[((long long)chunk * L.nbt + nblk0) * 64 + rem];
+            }
         }
     }
+    WV_STORE_B()
     __syncthreads();
 
-    floatx4 acc[2][NB];
+    floatx4 acc[MB][NB];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     const int m = lane & 15;
     const int kk = lane >> 4;
-    const float* wl = L.w + (long long)lane * 4;
 
     for (int tap = 0; tap < 9; ++tap) {
+        if (tap < 8) {
+            WV_LOAD_B(tap + 1)   // in flight while this tap computes
+        }
         const int dy = tap / 3;
         const int dx = tap - dy * 3;
-        const float* arow0 = lds_in + ((wave * 2 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
+        const float* arow0 = lds_in + ((row0 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            float4 av[2];
+            float4 av[MB];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
                 av[mb] = *reinterpret_cast<const float4*>(arow0 + mb * HALO_W * STRIDE + cb * 16);
             float4 bv[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                bv[nb] = *reinterpret_cast<const float4*>(
-                    wl + ((long long)(tap * CB + cb) * L.nbt + nblk0 + nb) * 256);
+            for (int nb = 0; nb < NB; ++nb) bv[nb] = lds_w[(cb * NB + nb) * 64 + lane];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].x, bv[nb].x,
@@ -126,6 +172,11 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                                                                        acc[mb][nb], 0, 0, 0);
                 }
         }
+        if (tap < 8) {
+            __syncthreads();   // every wave is done with this tap's B
+            WV_STORE_B()
+            __syncthreads();
+        }
     }
     if (SYM) {
 #pragma unroll
@@ -133,28 +184,31 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
             const int tap = chunk * 4 + kk;
             const int dy = tap / 3;
             const int dx = tap - dy * 3;
-            float av[2];
+            float av[MB];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-                av[mb] = tap < 9 ? lds_s[(wave * 2 + mb + dy) * HALO_W + m + dx] : 0.f;
+            for (int mb = 0; mb < MB; ++mb)
+                av[mb] = tap < 9 ? lds_s[(row0 + mb + dy) * HALO_W + m + dx] : 0.f;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const float bv = L.wsym[((long long)chunk * L.nbt + nblk0 + nb) * 64 + lane];
+                const float bv = lds_ws[(chunk * NB + nb) * 64 + lane];
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
+                for (int mb = 0; mb < MB; ++mb)
                     acc[mb][nb] =
                         __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv, acc[mb][nb], 0, 0, 0);
             }
         }
     }
 
+#undef WV_LOAD_B
+#undef WV_STORE_B
+
     // ---- epilogues.  Lane holds D[4*(lane/16) + i][lane % 16] of each block. ----
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
     if (MODE == CONV_RELU || MODE == CONV_TANH) {
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int r = r0 + wave * 2 + mb;
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = r0 + row0 + mb;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int ch = (nblk0 + nb) * 16 + col;
@@ -180,8 +234,8 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
         const float bo = L.bias[(nblk0 + 3) * 16 + col];
         const int wp = a.w >> a.cprev_up;
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-            const int r = r0 + wave * 2 + mb;
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = r0 + row0 + mb;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int c = c0 + rowq + i;
@@ -203,19 +257,17 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                 }
             }
         }
-    } else {  // CONV_HEAD: raw 3K outputs of every tile position -> LDS -> step-g positions
+    } else {  // CONV_HEAD: raw 3K outputs of the coded row of each wave -> LDS -> step-g positions
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                lds_head[((wave * 2 + mb) * TILE_W + rowq + i) * 17 + col] =
-                    acc[mb][0][i] + L.bias[col];
+        for (int i = 0; i < 4; ++i)
+            lds_head[(wave * TILE_W + rowq + i) * 17 + col] = acc[0][0][i] + L.bias[col];
         __syncthreads();
-        if (tid < TILE_H * TILE_W) {
-            const int r = r0 + tid / TILE_W;
+        if (tid < 4 * TILE_W) {
+            const int wv = tid / TILE_W;
+            const int r = r0 + wv * 2 + (a.step >> 1);
             const int c = c0 + tid % TILE_W;
             const int gr = a.step >> 1, gc = a.step & 1;
-            if (r < a.h && c < a.w && (r & 1) == gr && (c & 1) == gc) {
+            if (r < a.h && c < a.w && (c & 1) == gc) {
                 const float* v = lds_head + tid * 17;
                 const int K = a.K;
                 const int wg = (a.w - gc + 1) >> 1;
@@ -267,10 +319,21 @@ hipError_t dispatch_sym(const MfmaLayer& L, int mode, const ConvArgs& a, hipStre
                      : dispatch_mode<CIN, NB, false>(L, mode, a, s);
 }
 
+// Output blocks per workgroup.  Small subbands give few position tiles; there
+// the output channels are spread over more workgroups (each output's
+// accumulation order is unchanged, so the bits are too).
+inline int pick_nb(const MfmaLayer& L, int mode, const ConvArgs& a) {
+    if (mode == CONV_HEAD) return 1;
+    if (mode == CONV_LSTM) return 4;
+    const long long tiles = (long long)a.tiles_x * a.tiles_y * a.N;
+    int nb = L.nbt >= 4 ? 4 : L.nbt;
+    while (nb > 1 && tiles * (L.nbt / nb) < 512) nb >>= 1;
+    return nb;
+}
+
 template <int CIN>
 hipError_t dispatch_nb(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
-    int nb = (mode == CONV_HEAD) ? 1 : (L.nbt >= 4 ? 4 : L.nbt);
-    if (mode == CONV_LSTM) nb = 4;
+    const int nb = pick_nb(L, mode, a);
     switch (nb) {
         case 1: return dispatch_sym<CIN, 1>(L, mode, a, s);
         case 2: return dispatch_sym<CIN, 2>(L, mode, a, s);
