@@ -52,6 +52,10 @@ enum {
 
 typedef enum { WV_FP32 = 0, WV_BF16 = 1, WV_FP8 = 2 } wv_precision;
 
+/* Component family of the per-coefficient mixture.  Sec. 3.1 uses a Laplacian
+ * (mean and scale); the workload's default is a K-component Gaussian mixture. */
+typedef enum { WV_DIST_GAUSS = 0, WV_DIST_LAPLACE = 1 } wv_dist;
+
 /* Model hyper-parameters.  Sec. 3.1 (lifting), Sec. 3.2 (context model). */
 typedef struct wv_config {
     int levels;      /* J decomposition levels (3J+1 subbands)                 */
@@ -65,6 +69,7 @@ typedef struct wv_config {
     int cdf_bits;    /* CDF precision: tables sum to 2^cdf_bits (16)           */
     float sigma_min; /* lower bound of the mixture scales, symbol units        */
     int lift_int;    /* 1: predict/update outputs rounded (lossless lifting)   */
+    int dist;        /* wv_dist: mixture component family                     */
 } wv_config;
 
 /* One subband of the packed layout. type: 0 LL, 1 HL, 2 LH, 3 HH. */
@@ -162,11 +167,13 @@ int wv_context_params(const wv_model* m, const int16_t* d_q, int nplanes, int H,
                       float* d_params, void* stream);
 
 /*
- * 16-bit CDF tables of n discretised K-component Gaussian mixtures.  The
- * paper arithmetic-codes the symbols with the estimated distribution
- * (Sec. 3.1); the table format is this library's:
+ * 16-bit CDF tables of n discretised K-component mixtures.  The paper
+ * arithmetic-codes the symbols with the estimated distribution (Sec. 3.1);
+ * the table format is this library's:
  *   N_s = sym_max - sym_min + 1, F_max = 2^cdf_bits - N_s,
  *   C_j = sum_k w_k Phi((sym_min + j - 0.5 - mu_k) / sigma_k) / sum_k w_k,
+ *   Phi the standard normal CDF (dist = WV_DIST_GAUSS) or the standard
+ *   Laplace CDF (WV_DIST_LAPLACE, sigma the Laplace scale),
  *   F_j = floor(F_max * C_j) (exact value: from the upper tail where
  *   C_j > 1/2, never F_max), running maximum, cdf[j] = j + F_j, j = 0..N_s-1;
  *   cdf[N_s] = 2^cdf_bits stored as 0 (mod 2^16).  Every symbol has
@@ -174,8 +181,8 @@ int wv_context_params(const wv_model* m, const int16_t* d_q, int nplanes, int H,
  *   d_params : float [n][3K];  d_cdf : uint16 [n][N_s + 1].
  * Requires cdf_bits == 16 and N_s <= 255.
  */
-int wv_cdf_tables(const float* d_params, long long n, int mix_k, int sym_min, int sym_max,
-                  int cdf_bits, uint16_t* d_cdf, void* stream);
+int wv_cdf_tables(const float* d_params, long long n, int mix_k, int dist, int sym_min,
+                  int sym_max, int cdf_bits, uint16_t* d_cdf, void* stream);
 
 /* Write decoded symbol indices (symbol - sym_min) of step `step` of subband
  * `subband` into the packed symbols: d_sym uint8 [nplanes][n_g]. */
@@ -195,6 +202,20 @@ int wv_gather_symbols(const wv_config* cfg, const int16_t* d_q, int nplanes, int
 int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int nplanes,
                   int H, int W, float delta_L, float delta_H, void* d_scratch,
                   float* d_xhat, uint8_t* d_u8, void* stream);
+
+/*
+ * Subband impulse responses (Sec. 3.4) of one plane's quantised subbands
+ * d_q [H*W] (packed layout).  For every subband i, the largest |q_i| is placed
+ * into the i-th subband of an otherwise all-zero S x S pyramid, S = 2^levels
+ * (the level-J subbands are 1 x 1); its cell is the arg-max of |q_i|
+ * max-pooled by (H/S) x (W/S) windows, the first in raster order on ties.
+ * The pyramid is dequantised (/ Delta) and inverse transformed without the
+ * +128 offset.  d_out: float [3J+1][S][S].  d_scratch:
+ * wv_impulse_scratch_bytes() bytes.
+ */
+int wv_impulse_scratch_bytes(const wv_model* m, size_t* bytes);
+int wv_impulse_responses(const wv_model* m, const int16_t* d_q, int H, int W, float delta_L,
+                         float delta_H, void* d_scratch, float* d_out, void* stream);
 
 /*
  * Temporal Haar lifting over a GOP of T = 2^levels frames of n floats each

@@ -396,13 +396,21 @@ def _phi(z):
     return 0.5 * _erfc(-z / np.sqrt(2.0))
 
 
+def _laplace_cdf(z):
+    """Standard Laplace CDF: exp(z)/2 for z < 0, 1 - exp(-z)/2 otherwise (Sec. 3.1 uses a
+    Laplacian with a mean and a scale per coefficient)."""
+    return np.where(z < 0, 0.5 * np.exp(np.minimum(z, 0.0)), 1.0 - 0.5 * np.exp(-np.maximum(z, 0.0)))
+
+
 def cdf_tables(params, cfg):
-    """Integer CDF rows [n][N_s + 1] of the discretised Gaussian mixture.
+    """Integer CDF rows [n][N_s + 1] of the discretised mixture (Gaussian components, or
+    Laplacian components when cfg["dist"] == "laplace").
 
     The paper only says the symbols are arithmetic coded with the estimated
     distribution (Sec. 3.1).  Reading (a 16-bit table over the alphabet):
       T = 2^cdf_bits, N_s = sym_max - sym_min + 1 symbols, F_max = T - N_s;
-      C_j = sum_k w_k Phi((b_j - mu_k) / sigma_k) / sum_k w_k at the interior
+      C_j = sum_k w_k Phi((b_j - mu_k) / sigma_k) / sum_k w_k (Phi the standard
+      normal or standard Laplace CDF, sigma the Laplace scale) at the interior
       boundaries b_j = sym_min + j - 0.5, j = 1 .. N_s - 1 (the weights are
       renormalised because a stored softmax sums to 1 only up to rounding);
       F_j = floor(F_max * C_j), F_0 = 0, F_{N_s} = F_max;
@@ -411,21 +419,22 @@ def cdf_tables(params, cfg):
       table sums to T.
     The value is evaluated as in exact arithmetic: where C_j > 1/2 it is
     computed from the upper tail, F_j = F_max - ceil(F_max * (1 - C_j)), and
-    since 1 - C_j > 0 for a Gaussian the ceiling is at least 1.
+    since 1 - C_j > 0 for both families the ceiling is at least 1.
     Entry N_s (= T) is stored as T mod 2^16 = 0 in the uint16 tables.
     """
     K = cfg["mix_k"]
     Ns = cfg["sym_max"] - cfg["sym_min"] + 1
     T = 1 << cfg["cdf_bits"]
     Fmax = T - Ns
+    cdf1 = _laplace_cdf if cfg.get("dist", "gauss") == "laplace" else _phi
     p = np.asarray(params, np.float64).reshape(-1, 3 * K)
     w, mu, sg = p[:, :K], p[:, K:2 * K], p[:, 2 * K:]
     j = np.arange(1, Ns)
     b = cfg["sym_min"] + j - 0.5
     z = (b[None, :, None] - mu[:, None, :]) / sg[:, None, :]      # [n][Ns-1][K]
     wsum = w.sum(-1, keepdims=True)
-    lower = (w[:, None, :] * _phi(z)).sum(-1) / wsum
-    upper = (w[:, None, :] * _phi(-z)).sum(-1) / wsum
+    lower = (w[:, None, :] * cdf1(z)).sum(-1) / wsum
+    upper = (w[:, None, :] * cdf1(-z)).sum(-1) / wsum
     F_lo = np.floor(Fmax * lower)
     F_hi = Fmax - np.maximum(1.0, np.ceil(Fmax * upper))
     F = np.where(lower <= upper, F_lo, F_hi)

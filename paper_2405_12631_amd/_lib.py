@@ -15,6 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libwv.so")
 WV_OK, WV_EINVAL, WV_ESHAPE, WV_EORDER, WV_EDEVICE, WV_ECORRUPT, WV_EUNSUPPORTED, WV_ENOMEM = \
     0, -1, -2, -3, -4, -5, -6, -7
 WV_FP32, WV_BF16, WV_FP8 = 0, 1, 2
+WV_DIST_GAUSS, WV_DIST_LAPLACE = 0, 1
+DISTS = {"gauss": WV_DIST_GAUSS, "laplace": WV_DIST_LAPLACE}
 ERR_NAMES = {0: "WV_OK", -1: "WV_EINVAL", -2: "WV_ESHAPE", -3: "WV_EORDER", -4: "WV_EDEVICE",
              -5: "WV_ECORRUPT", -6: "WV_EUNSUPPORTED", -7: "WV_ENOMEM"}
 
@@ -29,7 +31,7 @@ class wv_config(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("lift_ch", ctypes.c_int), ("lift_layers", ctypes.c_int),
                 ("ctx_ch", ctypes.c_int), ("ctx_layers", ctypes.c_int), ("mix_k", ctypes.c_int),
                 ("sym_min", ctypes.c_int), ("sym_max", ctypes.c_int), ("cdf_bits", ctypes.c_int),
-                ("sigma_min", ctypes.c_float), ("lift_int", ctypes.c_int)]
+                ("sigma_min", ctypes.c_float), ("lift_int", ctypes.c_int), ("dist", ctypes.c_int)]
 
 
 class wv_subband(ctypes.Structure):
@@ -56,10 +58,12 @@ _SIGS = {
     "wv_workspace_bytes": (_I, [_P, _I, _I, _I, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)]),
     "wv_analyze": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P, _P]),
     "wv_context_params": (_I, [_P, _P, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
-    "wv_cdf_tables": (_I, [_P, _LL, _I, _I, _I, _I, _P, _P]),
+    "wv_cdf_tables": (_I, [_P, _LL, _I, _I, _I, _I, _I, _P, _P]),
     "wv_scatter_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_gather_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_synthesize": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P]),
+    "wv_impulse_scratch_bytes": (_I, [_P, ctypes.POINTER(_SZ)]),
+    "wv_impulse_responses": (_I, [_P, _P, _I, _I, _F, _F, _P, _P, _P]),
     "wv_temporal_haar_forward": (_I, [_P, _I, _LL, _P]),
     "wv_temporal_haar_inverse": (_I, [_P, _I, _LL, _P]),
     "wv_rans_encode": (_I, [_P, _I, _P, _LL, _P, _SZ, ctypes.POINTER(_SZ)]),

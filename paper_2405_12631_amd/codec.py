@@ -24,7 +24,8 @@ def make_config(cfg):
     return L.wv_config(levels=cfg["levels"], lift_ch=cfg["lift_ch"], lift_layers=cfg["lift_layers"],
                        ctx_ch=cfg["ctx_ch"], ctx_layers=cfg["ctx_layers"], mix_k=cfg["mix_k"],
                        sym_min=cfg["sym_min"], sym_max=cfg["sym_max"], cdf_bits=cfg["cdf_bits"],
-                       sigma_min=cfg["sigma_min"], lift_int=int(cfg.get("lift_int", 0)))
+                       sigma_min=cfg["sigma_min"], lift_int=int(cfg.get("lift_int", 0)),
+                       dist=L.DISTS[cfg.get("dist", "gauss")])
 
 
 def _ptr(t):
@@ -136,8 +137,8 @@ def cdf_tables(model, params, out=None):
     n = params.numel() // (3 * K)
     if out is None:
         out = torch.empty(n * (model.nsym + 1), dtype=torch.int16, device=params.device)
-    L.call("wv_cdf_tables", _ptr(params), n, K, model.cfg["sym_min"], model.cfg["sym_max"],
-           model.cfg["cdf_bits"], _ptr(out), _stream())
+    L.call("wv_cdf_tables", _ptr(params), n, K, model.c.dist, model.cfg["sym_min"],
+           model.cfg["sym_max"], model.cfg["cdf_bits"], _ptr(out), _stream())
     return out[:n * (model.nsym + 1)].view(n, model.nsym + 1)
 
 
@@ -167,6 +168,20 @@ def synthesize(model, ws, q=None, y=None, xhat=None, want_u8=False):
     L.call("wv_synthesize", model.h, _ptr(q), _ptr(y), N, H, W, dL, dH, _ptr(ws.scratch),
            _ptr(xhat), _ptr(u8), _stream())
     return xhat, u8
+
+
+def impulse_responses(model, q_plane, H, W):
+    """Subband impulse responses (Sec. 3.4) of one plane's packed symbols q_plane [H*W]
+    -> float [3J+1, S, S] with S = 2^levels."""
+    nb = ctypes.c_size_t()
+    L.call("wv_impulse_scratch_bytes", model.h, _byref(nb))
+    scratch = torch.empty(nb.value // 4 + 64, dtype=torch.float32, device=q_plane.device)
+    S = 1 << model.cfg["levels"]
+    out = torch.empty((3 * model.cfg["levels"] + 1, S, S), dtype=torch.float32, device=q_plane.device)
+    dL, dH = model.deltas()
+    L.call("wv_impulse_responses", model.h, _ptr(q_plane), H, W, dL, dH, _ptr(scratch), _ptr(out),
+           _stream())
+    return out
 
 
 def temporal_haar(frames, inverse=False):

@@ -54,6 +54,7 @@ static int check_cfg(const wv_config* c) {
     if (c->sym_min < -32768 || c->sym_max > 32767) return fail(WV_EINVAL, "alphabet exceeds int16");
     if (c->cdf_bits != 16) return fail(WV_EUNSUPPORTED, "cdf_bits must be 16");
     if (!(c->sigma_min > 0.f)) return fail(WV_EINVAL, "sigma_min must be > 0");
+    if (c->dist != WV_DIST_GAUSS && c->dist != WV_DIST_LAPLACE) return fail(WV_EINVAL, "bad dist");
     return WV_OK;
 }
 
@@ -511,9 +512,19 @@ extern "C" int wv_analyze(const wv_model* m, const uint8_t* d_x8, const float* d
     return WV_OK;
 }
 
+static int synth_impl(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H, int W,
+                      float dL, float dH, void* d_scratch, float* d_xhat, uint8_t* d_u8,
+                      float offset, void* stream);
+
 extern "C" int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H,
                              int W, float dL, float dH, void* d_scratch, float* d_xhat, uint8_t* d_u8,
                              void* stream) {
+    return synth_impl(m, d_q, d_y, N, H, W, dL, dH, d_scratch, d_xhat, d_u8, 128.0f, stream);
+}
+
+static int synth_impl(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H, int W,
+                      float dL, float dH, void* d_scratch, float* d_xhat, uint8_t* d_u8,
+                      float offset, void* stream) {
     if (!m) return fail(WV_EINVAL, "null model");
     if ((!d_q && !d_y) || !d_scratch || !d_xhat) return fail(WV_EINVAL, "null pointer");
     if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
@@ -571,8 +582,68 @@ extern "C" int wv_synthesize(const wv_model* m, const int16_t* d_q, const float*
         X = xo;
         xps = ops;
     }
-    HIPCHK(launch_finalize(d_xhat, d_u8, N * HW, s));
+    HIPCHK(launch_finalize(d_xhat, d_u8, N * HW, offset, s));
     return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// subband impulse responses (Sec. 3.4)
+// ---------------------------------------------------------------------------
+namespace {
+struct SirScratch { size_t keys, y, synth, total; };
+SirScratch sir_layout(const wv_config& c, int S) {
+    const int nsub = 3 * c.levels + 1;
+    SirScratch r;
+    r.keys = 0;
+    r.y = al(32);                                   // 32 u64 keys = 64 floats ... 256-byte aligned
+    r.synth = al(r.y + (size_t)nsub * S * S);
+    r.total = (r.synth * sizeof(float)) + scratch_layout(c, nsub, S, S).total;
+    return r;
+}
+}  // namespace
+
+extern "C" int wv_impulse_scratch_bytes(const wv_model* m, size_t* bytes) {
+    if (!m || !bytes) return fail(WV_EINVAL, "null pointer");
+    *bytes = sir_layout(m->cfg, 1 << m->cfg.levels).total;
+    return WV_OK;
+}
+
+extern "C" int wv_impulse_responses(const wv_model* m, const int16_t* d_q, int H, int W, float dL,
+                                    float dH, void* d_scratch, float* d_out, void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (!d_q || !d_scratch || !d_out) return fail(WV_EINVAL, "null pointer");
+    if (!(dL > 0.f) || !(dH > 0.f)) return fail(WV_EINVAL, "quantiser steps must be > 0");
+    std::vector<Sub> lay, play;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    const int S = 1 << m->cfg.levels;
+    rc = layout(m->cfg, S, S, play);
+    if (rc) return rc;
+    const int nsub = (int)lay.size();
+    if (nsub > MAX_SUB) return fail(WV_EUNSUPPORTED, "too many subbands");
+    SirMeta meta{};
+    meta.nsub = nsub;
+    meta.S = S;
+    meta.ph = H / S;
+    meta.pw = W / S;
+    long long max_n = 0;
+    for (int i = 0; i < nsub; ++i) {
+        meta.off[i] = lay[i].off;
+        meta.h[i] = lay[i].h;
+        meta.w[i] = lay[i].w;
+        meta.soff[i] = play[i].off;
+        meta.sw[i] = play[i].w;
+        const long long n = (long long)lay[i].h * lay[i].w;
+        max_n = n > max_n ? n : max_n;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const SirScratch sc = sir_layout(m->cfg, S);
+    float* base = (float*)d_scratch;
+    unsigned long long* keys = (unsigned long long*)(base + sc.keys);
+    float* y = base + sc.y;
+    HIPCHK(launch_sir_keys(d_q, keys, meta, max_n, s));
+    HIPCHK(launch_sir_pyramid(keys, meta, dL, dH, y, s));
+    return synth_impl(m, nullptr, y, nsub, S, S, dL, dH, base + sc.synth, d_out, nullptr, 0.0f, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,15 +736,16 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
     return WV_OK;
 }
 
-extern "C" int wv_cdf_tables(const float* d_params, long long n, int K, int sym_min, int sym_max,
-                             int cdf_bits, uint16_t* d_cdf, void* stream) {
+extern "C" int wv_cdf_tables(const float* d_params, long long n, int K, int dist, int sym_min,
+                             int sym_max, int cdf_bits, uint16_t* d_cdf, void* stream) {
     if (n < 0) return fail(WV_ESHAPE, "negative row count");
     if (n > 0 && (!d_params || !d_cdf)) return fail(WV_EINVAL, "null pointer");
     if (K < 1 || K > 4) return fail(WV_EUNSUPPORTED, "mix_k must be 1..4");
     const int nsym = sym_max - sym_min + 1;
     if (nsym < 2 || nsym > 255) return fail(WV_EUNSUPPORTED, "alphabet must have 2..255 symbols");
     if (cdf_bits != 16) return fail(WV_EUNSUPPORTED, "cdf_bits must be 16");
-    HIPCHK(launch_cdf(d_params, n, K, sym_min, nsym, d_cdf, (hipStream_t)stream));
+    if (dist != WV_DIST_GAUSS && dist != WV_DIST_LAPLACE) return fail(WV_EINVAL, "bad dist");
+    HIPCHK(launch_cdf(d_params, n, K, dist, sym_min, nsym, d_cdf, (hipStream_t)stream));
     return WV_OK;
 }
 

@@ -1,13 +1,13 @@
-// Discretised Gaussian-mixture -> 16-bit integer CDF tables.
+// Discretised mixture (Gaussian or Laplacian components) -> 16-bit integer CDF tables.
 //
 // Row n (one coefficient) has N_s + 1 entries cdf[j] = j + F_j with
 // F_j = floor(F_max * C_j), C_j the normalised mixture CDF at the boundary
 // sym_min + j - 0.5, F_max = 2^16 - N_s; entry N_s (= 2^16) is stored as 0.
 // The exact value of the floor is produced:
-//   * outside [j_lo, j_hi], where every component is at least 6 sigma away
-//     from the boundary, the value is known without evaluating Phi:
-//     C_j <= Phi(-6) < 1/F_max gives F_j = 0 below, and 0 < 1 - C_j <
-//     1/F_max gives F_j = F_max - 1 above;
+//   * outside [j_lo, j_hi], where every component is at least TZ scales away
+//     from the boundary (TZ = 6 Gaussian, 12 Laplace), the value is known
+//     without evaluating Phi: C_j <= Phi(-TZ) < 1/F_max gives F_j = 0 below,
+//     and 0 < 1 - C_j < 1/F_max gives F_j = F_max - 1 above;
 //   * inside, the lower tail sum is used when C_j <= 1/2, else the upper tail
 //     (F_j = F_max - ceil(F_max * (1 - C_j)), at least one count below F_max),
 //     so no digits are lost to 1 - tiny rounding to 1;
@@ -22,7 +22,15 @@ namespace {
 constexpr int ROWS = 64;
 constexpr int MAXE = 256;   // max entries per row (N_s + 1)
 
-template <int K>
+// Smaller tail of a standard component at |z|: Gaussian 0.5 erfc(|z|/sqrt 2),
+// Laplace 0.5 exp(-|z|).  TAILZ: |z| beyond which the tail is < 1/(2^16 F_max)
+// scale, i.e. 0 < tail * F_max < 1 (Gaussian 6: 1e-9; Laplace 12: 3e-6).
+template <int DIST>
+__device__ __forceinline__ float tail_of(float az) {
+    return DIST == WV_DIST_GAUSS ? 0.5f * erfcf(az * 0.70710678118654752f) : 0.5f * expf(-az);
+}
+
+template <int K, int DIST>
 __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, long long n, int smin,
                                              int nsym, uint16_t* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) uint16_t rows[];   // [ROWS][nsym + 1]
@@ -42,8 +50,9 @@ __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, 
             mu[k] = p[K + k];
             sg[k] = p[2 * K + k];
             S += w[k];
-            lo = fminf(lo, mu[k] - 6.0f * sg[k]);
-            hi = fmaxf(hi, mu[k] + 6.0f * sg[k]);
+            constexpr float TZ = DIST == WV_DIST_GAUSS ? 6.0f : 12.0f;
+            lo = fminf(lo, mu[k] - TZ * sg[k]);
+            hi = fmaxf(hi, mu[k] + TZ * sg[k]);
         }
         const float invS = 1.0f / S;
         const int Fmax = 65536 - nsym;
@@ -66,7 +75,7 @@ __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, 
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     const float z = (b - mu[k]) / sg[k];
-                    const float tail = 0.5f * erfcf(fabsf(z) * 0.70710678118654752f);
+                    const float tail = tail_of<DIST>(fabsf(z));
                     if (z < 0.f) {
                         L = fmaf(w[k], tail, L);
                         U = fmaf(w[k], 1.0f - tail, U);
@@ -104,20 +113,21 @@ __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, 
 
 }  // namespace
 
-hipError_t launch_cdf(const float* params, long long n, int K, int smin, int nsym, uint16_t* cdf,
-                      hipStream_t s) {
+hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smin, int nsym,
+                      uint16_t* cdf, hipStream_t s) {
     if (n == 0) return hipSuccess;
     if (nsym + 1 > MAXE || nsym < 2) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((n + ROWS - 1) / ROWS);
     const size_t lds = ((size_t)ROWS * (nsym + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
-    switch (K) {
-        case 1: hipLaunchKernelGGL(cdf_k<1>, dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); break;
-        case 2: hipLaunchKernelGGL(cdf_k<2>, dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); break;
-        case 3: hipLaunchKernelGGL(cdf_k<3>, dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); break;
-        case 4: hipLaunchKernelGGL(cdf_k<4>, dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); break;
-        default: return hipErrorInvalidValue;
+#define WV_CDF_CASE(KK, DD)                                                                   \
+    if (K == KK && dist == DD) {                                                              \
+        hipLaunchKernelGGL((cdf_k<KK, DD>), dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); \
+        return hipGetLastError();                                                             \
     }
-    return hipGetLastError();
+    WV_CDF_CASE(1, 0) WV_CDF_CASE(2, 0) WV_CDF_CASE(3, 0) WV_CDF_CASE(4, 0)
+    WV_CDF_CASE(1, 1) WV_CDF_CASE(2, 1) WV_CDF_CASE(3, 1) WV_CDF_CASE(4, 1)
+#undef WV_CDF_CASE
+    return hipErrorInvalidValue;
 }
 
 }  // namespace wv

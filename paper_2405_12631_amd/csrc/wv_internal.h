@@ -1,5 +1,5 @@
 // Internal declarations shared by the C ABI (wv_api.hip) and the kernels
-// (wv_conv.hip, wv_lift.hip, wv_cdf.hip, wv_misc.hip).  Not installed.
+// (wv_conv.hip, wv_lift.hip, wv_cdf.hip).  Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,12 +98,25 @@ hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plan
                            float dL, float dH, int smin, int smax, int* clip, hipStream_t s);
 hipError_t launch_dequantize(const int16_t* q, float* y, int N, long long per_plane,
                              long long n_ll, float dL, float dH, hipStream_t s);
-hipError_t launch_finalize(float* x, uint8_t* u8, long long n, hipStream_t s);
+hipError_t launch_finalize(float* x, uint8_t* u8, long long n, float offset, hipStream_t s);
+// Subband impulse responses.  Per subband i: offset and size of q_i in the
+// image's packed layout, offset and width of subband i in the S x S pyramid;
+// (ph, pw) = (H / S, W / S) is the max-pooling window.
+constexpr int MAX_SUB = 25;
+struct SirMeta {
+    long long off[MAX_SUB], soff[MAX_SUB];
+    int h[MAX_SUB], w[MAX_SUB], sw[MAX_SUB];
+    int nsub, S, ph, pw;
+};
+hipError_t launch_sir_keys(const int16_t* q, unsigned long long* keys, const SirMeta& m,
+                           long long max_n, hipStream_t s);
+hipError_t launch_sir_pyramid(const unsigned long long* keys, const SirMeta& m, float dL, float dH,
+                              float* y, hipStream_t s);
 hipError_t launch_scatter(const uint8_t* sym, int16_t* q, int N, long long q_ps, long long off,
                           int h, int w, int step, int smin, hipStream_t s);
 hipError_t launch_gather(const int16_t* q, uint8_t* sym, int N, long long q_ps, long long off,
                          int h, int w, int step, int smin, hipStream_t s);
-hipError_t launch_cdf(const float* params, long long n, int K, int smin, int nsym,
+hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smin, int nsym,
                       uint16_t* cdf, hipStream_t s);
 hipError_t launch_thaar(float* f, float* tmp, int T, long long n, int inverse, hipStream_t s);
 

@@ -116,10 +116,10 @@ __global__ __launch_bounds__(BLK) void dequantize_k(const int16_t* __restrict__ 
 }
 
 __global__ __launch_bounds__(BLK) void finalize_k(float* __restrict__ x, uint8_t* __restrict__ u8,
-                                                 long long n) {
+                                                 long long n, float offset) {
     const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
     if (i >= n) return;
-    const float v = x[i] + 128.0f;
+    const float v = x[i] + offset;
     x[i] = v;
     if (u8) u8[i] = (uint8_t)fminf(fmaxf(rintf(v), 0.f), 255.f);
 }
@@ -189,7 +189,70 @@ __global__ __launch_bounds__(BLK) void thaar_k(float* __restrict__ f, int T, lon
     for (int t = 0; t < T; ++t) f[(long long)t * n + i] = o[t];
 }
 
+// Subband impulse responses: per subband the key max over elements of
+// (|q| << 32) | (0xffffffff - pooled cell index): the largest magnitude, and
+// among equal magnitudes the first pooled cell in raster order.  atomicMax is
+// order-independent, so the result is deterministic.
+__global__ __launch_bounds__(BLK) void sir_keys_k(const int16_t* __restrict__ q,
+                                                 unsigned long long* __restrict__ keys,
+                                                 const SirMeta m) {
+    const int i = blockIdx.y;
+    const int h = m.h[i], w = m.w[i], sw = m.sw[i];
+    const long long n = (long long)h * w;
+    unsigned long long best = 0;
+    for (long long e = (long long)blockIdx.x * BLK + threadIdx.x; e < n; e += (long long)gridDim.x * BLK) {
+        const int r = (int)(e / w), c = (int)(e % w);
+        const int v = abs((int)q[m.off[i] + e]);
+        const unsigned cell = (unsigned)((r / m.ph) * sw + (c / m.pw));
+        const unsigned long long key = ((unsigned long long)v << 32) | (0xffffffffull - cell);
+        best = key > best ? key : best;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_down(best, o);
+        best = other > best ? other : best;
+    }
+    if ((threadIdx.x & 63) == 0 && best) atomicMax(keys + i, best);
+}
+
+// One S x S pyramid per subband: zero except the subband's own cell, which holds
+// max |q_i| / Delta.  y: [nsub][S*S] packed in the S x S layout.
+__global__ __launch_bounds__(BLK) void sir_pyramid_k(const unsigned long long* __restrict__ keys,
+                                                    const SirMeta m, float dL, float dH,
+                                                    float* __restrict__ y) {
+    const int i = blockIdx.y;
+    const int SS = m.S * m.S;
+    for (int e = threadIdx.x; e < SS; e += BLK) y[(long long)i * SS + e] = 0.f;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long key = keys[i];
+        const float v = (float)(unsigned)(key >> 32);
+        const unsigned cell = key ? 0xffffffffu - (unsigned)(key & 0xffffffffull) : 0u;
+        y[(long long)i * SS + m.soff[i] + cell] = v / (i == 0 ? dL : dH);
+    }
+}
+
+__global__ void fill_u64_k(unsigned long long* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_sir_keys(const int16_t* q, unsigned long long* keys, const SirMeta& m,
+                           long long max_n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u64_k, dim3(1), dim3(64), 0, s, keys, m.nsub);
+    unsigned gx = (unsigned)((max_n + BLK - 1) / BLK);
+    if (gx > 1024) gx = 1024;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(sir_keys_k, dim3(gx, m.nsub), dim3(BLK), 0, s, q, keys, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_sir_pyramid(const unsigned long long* keys, const SirMeta& m, float dL, float dH,
+                              float* y, hipStream_t s) {
+    hipLaunchKernelGGL(sir_pyramid_k, dim3(1, m.nsub), dim3(BLK), 0, s, keys, m, dL, dH, y);
+    return hipGetLastError();
+}
 
 hipError_t launch_lift_first(const VecLayer& L, CView z, int N, int h, int w, float* a1,
                              hipStream_t s) {
@@ -243,9 +306,9 @@ hipError_t launch_dequantize(const int16_t* q, float* y, int N, long long per_pl
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(float* x, uint8_t* u8, long long n, hipStream_t s) {
+hipError_t launch_finalize(float* x, uint8_t* u8, long long n, float offset, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_k, dim3(nblocks(n)), dim3(BLK), 0, s, x, u8, n);
+    hipLaunchKernelGGL(finalize_k, dim3(nblocks(n)), dim3(BLK), 0, s, x, u8, n, offset);
     return hipGetLastError();
 }
 

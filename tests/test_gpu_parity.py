@@ -248,3 +248,49 @@ def test_device_entry_points_reject_bad_calls(small):
     rc = L.lib().wv_context_params(small["model"].h, c._ptr(q), 1, 62, 64, 0, 0, c._ptr(ws.state),
                                    c._ptr(ws.scratch), c._ptr(ws.params), c._stream())
     assert rc == L.WV_ESHAPE
+
+
+def test_laplace_model_params_cdf_and_roundtrip():
+    """The paper's Laplacian probability model (K = 1) end to end."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("laplace K=1")
+    cfg = get_config("gray64", mix_k=1, dist="laplace")
+    model, w = model_for(cfg)
+    x = gradient_noise_image(64, 64, seed=1)[None]
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    ws = codec.Workspace(model, 1, 64, 64)
+    got = codec.params_all(model, q_to_device(qs), ws)
+    ref = O.context_params_all(qs, cfg, w)
+    for i in range(len(ref)):
+        for g in range(4):
+            assert param_err(got[i][g].cpu().numpy(), ref[i][g], 1) <= PARAM_RTOL, (i, g)
+            if i in (0, 6):
+                cdf = codec.cdf_tables(model, got[i][g])
+                check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[i][g].cpu().numpy(), cfg)
+    data, q_enc = codec.encode(model, x)
+    _, _, q_dec = codec.decode(model, data)
+    assert torch.equal(q_enc, q_dec)
+
+
+def test_subband_impulse_responses_match_oracle():
+    """Sec. 3.4 impulse responses of the 13 subbands on a 16 x 16 grid."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("impulse responses")
+    cfg = get_config("ycbcr512x768")
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(64, 96, planes=1, seed=8)
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    got = codec.impulse_responses(model, q_to_device(qs)[0], 64, 96).cpu().numpy()
+    ref = O.subband_impulse_responses(qs, cfg, w, size=16)
+    assert got.shape == (13, 16, 16)
+    assert np.max(np.abs(got - ref)) <= XHAT_ATOL
+    # A tie: two equal maxima in LL -> the first pooled cell in raster order wins.
+    qt = [q.copy() for q in qs]
+    qt[0][:] = 0
+    qt[0][0, 3, 5] = 9
+    qt[0][0, 1, 2] = -9
+    got = codec.impulse_responses(model, q_to_device(qt)[0], 64, 96).cpu().numpy()
+    ref = O.subband_impulse_responses(qt, cfg, w, size=16)
+    assert np.max(np.abs(got - ref)) <= XHAT_ATOL

@@ -76,8 +76,9 @@ def test_shape_and_argument_errors():
     nb = ctypes.c_size_t()
     assert L.lib().wv_pack_bytes(ctypes.byref(c), 9, ctypes.byref(nb)) == L.WV_EUNSUPPORTED
     # GPU entry points reject bad arguments on the host before any launch.
-    assert L.lib().wv_cdf_tables(None, 5, 3, -64, 64, 16, None, None) == L.WV_EINVAL
-    assert L.lib().wv_cdf_tables(None, 0, 3, -64, 64, 12, None, None) == L.WV_EUNSUPPORTED
+    assert L.lib().wv_cdf_tables(None, 5, 3, 0, -64, 64, 16, None, None) == L.WV_EINVAL
+    assert L.lib().wv_cdf_tables(None, 0, 3, 0, -64, 64, 12, None, None) == L.WV_EUNSUPPORTED
+    assert L.lib().wv_cdf_tables(None, 0, 3, 7, -64, 64, 16, None, None) == L.WV_EINVAL
     assert L.lib().wv_temporal_haar_forward(None, 6, 10, None) == L.WV_ESHAPE
     assert L.lib().wv_context_params(None, None, 1, 64, 64, 0, 0, None, None, None, None) == L.WV_EINVAL
 

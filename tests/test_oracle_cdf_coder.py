@@ -121,3 +121,55 @@ def test_rans_reference_edge_cases(cfg_small):
     assert np.array_equal(O.rans_decode_ref(cdf, data, 50), idx)
     with pytest.raises(ValueError):
         O.rans_decode_ref(cdf, data[:3], 50)
+
+
+def _exact_laplace_row(p, cfg):
+    """High-precision floor(F_max * C_j) for a Laplace mixture, from its definition."""
+    K = cfg["mix_k"]
+    Ns = cfg["sym_max"] - cfg["sym_min"] + 1
+    Fmax = (1 << cfg["cdf_bits"]) - Ns
+
+    def lap(z):
+        return mpmath.exp(z) / 2 if z < 0 else 1 - mpmath.exp(-z) / 2
+
+    ws = [mpmath.mpf(float(p[k])) for k in range(K)]
+    wsum = mpmath.fsum(ws)
+    row = [0]
+    for j in range(1, Ns):
+        b = mpmath.mpf(cfg["sym_min"] + j) - mpmath.mpf("0.5")
+        zs = [(b - mpmath.mpf(float(p[K + k]))) / mpmath.mpf(float(p[2 * K + k])) for k in range(K)]
+        c = mpmath.fsum(ws[k] * lap(zs[k]) for k in range(K)) / wsum
+        if c <= mpmath.mpf("0.5"):
+            row.append(j + int(mpmath.floor(Fmax * c)))
+        else:
+            t = mpmath.fsum(ws[k] * lap(-zs[k]) for k in range(K)) / wsum
+            row.append(j + Fmax - int(mpmath.ceil(Fmax * t)))
+    row.append(1 << cfg["cdf_bits"])
+    return np.array(row, np.int64)
+
+
+def test_cdf_laplace_matches_high_precision_and_scipy(cfg_small):
+    import scipy.stats
+    cfg1 = dict(cfg_small, mix_k=1, dist="laplace")
+    rng = np.random.default_rng(26)
+    mu = rng.uniform(-40, 40, 30)
+    b = np.exp(rng.uniform(np.log(0.11), np.log(30), 30))
+    p = np.stack([np.ones(30), mu, b], 1)
+    got = O.cdf_tables(p, cfg1)
+    for n in range(p.shape[0]):
+        np.testing.assert_array_equal(got[n], _exact_laplace_row(p[n], cfg1))
+    edges = np.arange(1, 129) - 64.5
+    c = scipy.stats.laplace.cdf(edges[None], loc=mu[:, None], scale=b[:, None])
+    ok = c < 0.5
+    want = np.arange(1, 129)[None] + np.floor(65407 * c)
+    assert np.array_equal(got[:, 1:129][ok], want[ok])
+    # Laplace mixtures, and the invariants on extreme parameters.
+    cfg3 = dict(cfg_small, dist="laplace")
+    p3 = _random_params(rng, 2000)
+    cdf = O.cdf_tables(p3, cfg3)
+    for n in range(6):
+        np.testing.assert_array_equal(cdf[n], _exact_laplace_row(p3[n], cfg3))
+    freq = np.diff(cdf, axis=1)
+    assert np.all(freq >= 1) and np.all(cdf[:, -1] == 65536) and np.all(cdf[:, 0] == 0)
+    # The two families differ (a dropped family switch would pass the checks above).
+    assert not np.array_equal(cdf, O.cdf_tables(p3, cfg_small))
