@@ -22,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
 HBM_PEAK_GBS = 8000.0
 
 
@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="context-conv precision (lifting and CDFs stay FP32)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path (run with --gpus 1)",
@@ -81,7 +83,9 @@ def main():
     cfg = get_config("ycbcr512x768")
     H, W, N = cfg["H"], cfg["W"], cfg["planes"]
     w = make_weights(cfg)
-    model = codec.Model(cfg, pack_weights(cfg, w))
+    from paper_2405_12631_amd import WV_BF16, WV_FP32
+    prec = WV_BF16 if args.precision == "bf16" else WV_FP32
+    model = codec.Model(cfg, pack_weights(cfg, w), precision=prec)
     x = sinusoid_1f_planes(H, W, planes=N, seed=cfg["seed_image"])
     ws = codec.Workspace(model, N, H, W)
     q_known, _, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws)
@@ -138,10 +142,12 @@ def main():
     ctx_flops = context_flops_per_coef(cfg) * H * W * N
     ctx_time = ctx_ms.sum(axis=1).mean() * 1e-3
     n_ctx_launch = nsub * (cfg["ctx_layers"] * 4) + nsub      # step layers + one LSTM per subband
+    peak = MFMA_PEAK_TFLOPS[args.precision]
+    kname = "conv3x3_mfma_bf16" if args.precision == "bf16" else "conv3x3_mfma_f32"
     roof = dict(bound="mfma", achieved=round(ctx_flops / ctx_time / 1e12, 3),
-                peak=MFMA_FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                frac=round(ctx_flops / ctx_time / 1e12 / MFMA_FP32_PEAK_TFLOPS, 4), traffic=None,
-                kernel="conv3x3_mfma_f32 (context model: ConvLSTM + step stacks)",
+                peak=peak, unit="TFLOP/s",
+                frac=round(ctx_flops / ctx_time / 1e12 / peak, 4), traffic=None,
+                kernel=f"{kname} (context model: ConvLSTM + step stacks)",
                 flops_per_decode=ctx_flops, launches_per_decode=n_ctx_launch,
                 avg_launch_us=round(ctx_time / n_ctx_launch * 1e6, 2))
 
@@ -149,10 +155,12 @@ def main():
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
         value=round(mpx, 4), unit="Mpixel/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32", data="synthetic",
+        dtype="f32" if args.precision == "fp32" else "bf16 context convs (fp32 accumulate), fp32 lifting/cdf",
+        data="synthetic",
         config=dict(workload="ycbcr512x768: one 512x768 3-plane YCbCr image, 1/f sinusoids + noise "
                              "(seed 2), 4-level CNN lifting (32 ch), 64-ch 4-layer context stacks, "
-                             "K=3 mixture, step 4, FP32, batch 1, coder elided",
+                             f"K=3 mixture, step 4, {args.precision.upper()} context, batch 1, "
+                             "coder elided",
                     batch=1, planes=N, H=H, W=W),
         p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
         stage_ms=dict(context=round(float(ctx_ms.sum(1).mean()), 3),

@@ -173,6 +173,62 @@ MfmaRef pack_mfma(PackBuf& pb, const float* blob, const ConvShape& s, int has_sy
     return r;
 }
 
+static uint16_t host_f2bf(float f) {   // round to nearest even
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// BF16 layer: B fragments of 8 consecutive K per lane, K chunk = 32 channels.
+// Stored in the float pack buffer; offsets count floats, so 2 bf16 per float.
+MfmaRef pack_mfma16(PackBuf& pb, const float* blob, const ConvShape& s, int has_sym, bool lstm,
+                    int C) {
+    MfmaRef r;
+    r.cin = s.cin - has_sym;
+    r.cout = s.cout;
+    r.nbt = (s.cout + 15) / 16;
+    r.has_sym = has_sym;
+    const int CC = r.cin / 32;
+    const int cin_total = s.cin;
+    const float* W = blob + s.w_off;
+    const float* B = blob + s.b_off;
+    r.w = pb.add((size_t)9 * CC * r.nbt * 64 * 4);          // 8 bf16 = 4 floats per lane
+    r.wsym = has_sym ? pb.add((size_t)r.nbt * 64 * 4) : 0;
+    r.bias = pb.add((size_t)r.nbt * 16);
+    uint16_t* pw = reinterpret_cast<uint16_t*>(pb.data.data() + r.w);
+    for (int tap = 0; tap < 9; ++tap)
+        for (int cc = 0; cc < CC; ++cc)
+            for (int nb = 0; nb < r.nbt; ++nb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 8; ++j) {
+                        const int kk = lane >> 4, nn = lane & 15;
+                        const int k = 32 * cc + 8 * kk + j;
+                        const int nc = nb * 16 + nn;
+                        float v = 0.f;
+                        if (nc < s.cout)
+                            v = W[((long long)perm_col(nc, C, lstm) * cin_total + has_sym + k) * 9 + tap];
+                        pw[((((size_t)(tap * CC + cc) * r.nbt + nb) * 64 + lane) * 8) + j] = host_f2bf(v);
+                    }
+    if (has_sym) {
+        uint16_t* ps = reinterpret_cast<uint16_t*>(pb.data.data() + r.wsym);
+        for (int nb = 0; nb < r.nbt; ++nb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int kk = lane >> 4, nn = lane & 15;
+                    const int tap = 8 * kk + j;
+                    const int nc = nb * 16 + nn;
+                    float v = 0.f;
+                    if (tap < 9 && nc < s.cout)
+                        v = W[((long long)perm_col(nc, C, lstm) * cin_total + 0) * 9 + tap];
+                    ps[((size_t)nb * 64 + lane) * 8 + j] = host_f2bf(v);
+                }
+    }
+    float* pbias = pb.data.data() + r.bias;
+    for (int nc = 0; nc < s.cout; ++nc) pbias[nc] = B[perm_col(nc, C, lstm)];
+    return r;
+}
+
 VecRef pack_vec_first(PackBuf& pb, const float* blob, const ConvShape& s) {
     VecRef r;
     r.ch = s.cout;
@@ -204,7 +260,8 @@ struct HostModel {
     std::vector<MfmaRef> ctx[4][4];
 };
 
-HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c) {
+// Context layers are packed for the precision's kernel; lifting is always FP32.
+HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c, int precision) {
     const Manifest mf = make_manifest(c);
     HostModel hm;
     for (int f = 0; f < 4; ++f) {
@@ -214,12 +271,13 @@ HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c) {
             hm.lift_mid[f].push_back(pack_mfma(pb, blob, v[l], 0, false, 0));
         hm.lift_last[f] = pack_vec_last(pb, blob, v.back());
     }
-    hm.lstm = pack_mfma(pb, blob, mf.lstm, 1, true, c.ctx_ch);
+    auto ctxpack = precision == WV_BF16 ? pack_mfma16 : pack_mfma;
+    hm.lstm = ctxpack(pb, blob, mf.lstm, 1, true, c.ctx_ch);
     for (int t = 0; t < 4; ++t)
         for (int g = 0; g < 4; ++g) {
             const auto& v = mf.ctx[t][g];
             for (size_t l = 0; l < v.size(); ++l)
-                hm.ctx[t][g].push_back(pack_mfma(pb, blob, v[l], (l == 0 && g > 0) ? 1 : 0, false, 0));
+                hm.ctx[t][g].push_back(ctxpack(pb, blob, v[l], (l == 0 && g > 0) ? 1 : 0, false, 0));
         }
     return hm;
 }
@@ -231,9 +289,20 @@ struct wv_model {
     int precision;
     VecLayer lift_first[4], lift_last[4];
     std::vector<MfmaLayer> lift_mid[4];
-    MfmaLayer lstm;
+    MfmaLayer lstm;                      // WV_FP32
     std::vector<MfmaLayer> ctx[4][4];
+    MfmaLayer16 lstm16;                  // WV_BF16
+    std::vector<MfmaLayer16> ctx16[4][4];
 };
+
+static int check_precision(const wv_config* c, int precision) {
+    if (precision == WV_FP32) return WV_OK;
+    if (precision == WV_BF16) {
+        if (c->ctx_ch % 32) return fail(WV_EUNSUPPORTED, "BF16 context needs ctx_ch of 32 or 64");
+        return WV_OK;
+    }
+    return fail(WV_EUNSUPPORTED, "precision %d is not implemented", precision);
+}
 
 extern "C" int wv_weights_count(const wv_config* cfg, long long* n_floats) {
     int rc = check_cfg(cfg);
@@ -243,21 +312,22 @@ extern "C" int wv_weights_count(const wv_config* cfg, long long* n_floats) {
     return WV_OK;
 }
 
-static size_t pack_floats(const wv_config& c) {
+static size_t pack_floats(const wv_config& c, int precision) {
     // Pack a zero blob to measure the layout size (host only, cheap).
     const Manifest mf = make_manifest(c);
     std::vector<float> zero((size_t)mf.total, 0.f);
     PackBuf pb;
-    pack_all(pb, zero.data(), c);
+    pack_all(pb, zero.data(), c, precision);
     return pb.data.size();
 }
 
 extern "C" int wv_pack_bytes(const wv_config* cfg, int precision, size_t* bytes) {
     int rc = check_cfg(cfg);
     if (rc) return rc;
-    if (precision != WV_FP32) return fail(WV_EUNSUPPORTED, "only WV_FP32 is implemented");
+    rc = check_precision(cfg, precision);
+    if (rc) return rc;
     if (!bytes) return fail(WV_EINVAL, "null output");
-    *bytes = pack_floats(*cfg) * sizeof(float);
+    *bytes = pack_floats(*cfg, precision) * sizeof(float);
     return WV_OK;
 }
 
@@ -267,7 +337,8 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
     int rc = check_cfg(cfg);
     if (rc) return rc;
     if (!d_weights || !d_pack || !out) return fail(WV_EINVAL, "null pointer");
-    if (precision != WV_FP32) return fail(WV_EUNSUPPORTED, "only WV_FP32 is implemented");
+    rc = check_precision(cfg, precision);
+    if (rc) return rc;
     const Manifest mf = make_manifest(*cfg);
     if (n_floats != mf.total)
         return fail(WV_EINVAL, "weight blob has %lld floats, config needs %lld", n_floats, mf.total);
@@ -276,7 +347,7 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
     HIPCHK(hipMemcpyAsync(blob.data(), d_weights, blob.size() * sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     PackBuf pb;
-    HostModel hm = pack_all(pb, blob.data(), *cfg);
+    HostModel hm = pack_all(pb, blob.data(), *cfg, precision);
     if (pb.data.size() * sizeof(float) > pack_bytes)
         return fail(WV_ENOMEM, "pack buffer has %zu bytes, needs %zu", pack_bytes,
                     pb.data.size() * sizeof(float));
@@ -288,6 +359,11 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
                          r.cin, r.cout, r.nbt, r.has_sym};
     };
     auto vec = [&](const VecRef& r) { return VecLayer{base + r.w, base + r.bias, r.ch}; };
+    auto mfma16 = [&](const MfmaRef& r) {
+        return MfmaLayer16{reinterpret_cast<const uint16_t*>(base + r.w),
+                           r.has_sym ? reinterpret_cast<const uint16_t*>(base + r.wsym) : nullptr,
+                           base + r.bias, r.cin, r.cout, r.nbt, r.has_sym};
+    };
     wv_model* m = new wv_model();
     m->cfg = *cfg;
     m->precision = precision;
@@ -296,10 +372,17 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
         m->lift_last[f] = vec(hm.lift_last[f]);
         for (auto& r : hm.lift_mid[f]) m->lift_mid[f].push_back(mfma(r));
     }
-    m->lstm = mfma(hm.lstm);
-    for (int t = 0; t < 4; ++t)
-        for (int g = 0; g < 4; ++g)
-            for (auto& r : hm.ctx[t][g]) m->ctx[t][g].push_back(mfma(r));
+    if (precision == WV_BF16) {
+        m->lstm16 = mfma16(hm.lstm);
+        for (int t = 0; t < 4; ++t)
+            for (int g = 0; g < 4; ++g)
+                for (auto& r : hm.ctx[t][g]) m->ctx16[t][g].push_back(mfma16(r));
+    } else {
+        m->lstm = mfma(hm.lstm);
+        for (int t = 0; t < 4; ++t)
+            for (int g = 0; g < 4; ++g)
+                for (auto& r : hm.ctx[t][g]) m->ctx[t][g].push_back(mfma(r));
+    }
     *out = m;
     return WV_OK;
 }
@@ -665,6 +748,7 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
     if (ng == 0) return WV_OK;   // a 1-wide subband has no positions at this step
     hipStream_t s = (hipStream_t)stream;
     const int C = m->cfg.ctx_ch;
+    const bool bf16 = m->precision == WV_BF16;   // h and activations stored as BF16
     const long long HW = (long long)H * W;
     const size_t SS = state_floats(m->cfg, N, H, W);
     const Sub& S = lay[i];
@@ -697,15 +781,23 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
             a.cprev_ps = (long long)P.h * P.w * C;
             a.cprev_up = up;
         }
-        HIPCHK(launch_conv(m->lstm, CONV_LSTM, a, s));
+        if (bf16) {
+            a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+            a.in = nullptr;
+            a.h16_out = reinterpret_cast<uint16_t*>(hcur);
+            a.h_out = nullptr;
+            HIPCHK(launch_conv_bf16(m->lstm16, CONV_LSTM, a, s));
+        } else {
+            HIPCHK(launch_conv(m->lstm, CONV_LSTM, a, s));
+        }
     }
     float* base = (float*)d_scratch;
     const Scratch sc = scratch_layout(m->cfg, N, H, W);
     float* act[2] = {base + sc.act0, base + sc.act1};
-    const std::vector<MfmaLayer>& stack = m->ctx[S.type][g];
+    const size_t nlayers = bf16 ? m->ctx16[S.type][g].size() : m->ctx[S.type][g].size();
     const float* in = hcur;
-    for (size_t l = 0; l < stack.size(); ++l) {
-        const bool last = l + 1 == stack.size();
+    for (size_t l = 0; l < nlayers; ++l) {
+        const bool last = l + 1 == nlayers;
         ConvArgs a{};
         a.in = in;
         a.in_ps = st_ps;
@@ -723,15 +815,23 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
             a.out = act[l & 1];
             a.out_ps = st_ps;
             a.out_cs = C;
-            HIPCHK(launch_conv(stack[l], CONV_RELU, a, s));
-            in = act[l & 1];
         } else {
             a.params = d_params;
             a.step = g;
             a.K = m->cfg.mix_k;
             a.sigma_min = m->cfg.sigma_min;
-            HIPCHK(launch_conv(stack[l], CONV_HEAD, a, s));
         }
+        const int mode = last ? CONV_HEAD : CONV_RELU;
+        if (bf16) {
+            a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+            a.in = nullptr;
+            a.out16 = reinterpret_cast<uint16_t*>(a.out);
+            a.out = nullptr;
+            HIPCHK(launch_conv_bf16(m->ctx16[S.type][g][l], mode, a, s));
+        } else {
+            HIPCHK(launch_conv(m->ctx[S.type][g][l], mode, a, s));
+        }
+        if (!last) in = act[l & 1];
     }
     return WV_OK;
 }

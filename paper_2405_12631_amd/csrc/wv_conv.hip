@@ -37,7 +37,10 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     constexpr int BV4 = CB * NB * 64;        // float4 of B per tap for this workgroup's N blocks
     constexpr int BPT = (BV4 + 255) / 256;   // float4 per thread
     constexpr int MB = (MODE == CONV_HEAD) ? 1 : 2;   // head: only the row parity its step codes
-    __shared__ __attribute__((aligned(16))) float lds_in[HALO * STRIDE];
+    // Input halo; after the MFMA loop it holds the output tile (RELU/TANH epilogue).
+    constexpr int LDS_IN = HALO * STRIDE > TILE_H * TILE_W * (NB * 16 + 4) ? HALO * STRIDE
+                                                                            : TILE_H * TILE_W * (NB * 16 + 4);
+    __shared__ __attribute__((aligned(16))) float lds_in[LDS_IN];
     __shared__ __attribute__((aligned(16))) float4 lds_w[BV4];
     __shared__ float lds_s[SYM ? HALO : 1];
     __shared__ float lds_ws[SYM ? 3 * NB * 64 : 1];
@@ -206,23 +209,34 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
     if (MODE == CONV_RELU || MODE == CONV_TANH) {
+        // Stage the output tile [128 positions][16 NB channels] in LDS (reusing the
+        // halo buffer), then write float4 chunks: full, coalesced lines.
+        constexpr int OS = NB * 16 + 4;
+        static_assert(TILE_H * TILE_W * OS <= LDS_IN, "output tile does not fit the halo buffer");
+        __syncthreads();
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const int r = r0 + row0 + mb;
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const int ch = (nblk0 + nb) * 16 + col;
-                const float b = L.bias[ch];
+                const float b = L.bias[(nblk0 + nb) * 16 + col];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int c = c0 + rowq + i;
-                    if (r < a.h && c < a.w && ch < L.cout) {
-                        float v = acc[mb][nb][i] + b;
-                        v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
-                        a.out[(long long)n * a.out_ps + ((long long)r * a.w + c) * a.out_cs + ch] = v;
-                    }
+                    float v = acc[mb][nb][i] + b;
+                    v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
+                    lds_in[((row0 + mb) * TILE_W + rowq + i) * OS + nb * 16 + col] = v;
                 }
             }
+        __syncthreads();
+        constexpr int V4 = NB * 4;   // float4 chunks per position
+        for (int idx = tid; idx < TILE_H * TILE_W * V4; idx += 256) {
+            const int pos = idx / V4;
+            const int c4 = idx - pos * V4;
+            const int r = r0 + pos / TILE_W;
+            const int c = c0 + pos % TILE_W;
+            if (r < a.h && c < a.w && (nblk0 * 16 + c4 * 4) < L.cout)
+                *reinterpret_cast<float4*>(a.out + (long long)n * a.out_ps +
+                                           ((long long)r * a.w + c) * a.out_cs + nblk0 * 16 + c4 * 4) =
+                    *reinterpret_cast<const float4*>(lds_in + pos * OS + c4 * 4);
         }
     } else if (MODE == CONV_LSTM) {
         // Block nb of this workgroup is gate nb (input, forget, cell, output)

@@ -1,0 +1,348 @@
+// 3x3 convolution as an implicit GEMM on the gfx950 matrix cores, BF16
+// operands with FP32 accumulation (precision variant of the context model).
+//
+// Same GEMM view and epilogues as the FP32 kernel (wv_conv.hip); what changes
+// with v_mfma_f32_16x16x32_bf16 is the balance: one instruction covers 32
+// input channels, so operand traffic rather than the matrix pipe becomes the
+// limit.  The tile is therefore taller: a workgroup owns 16 x 16 positions,
+// each of its 4 waves 4 rows x (16 NB) channels (16 accumulators for NB = 4).
+// A fragments: one 16-byte LDS read = 8 channels of one position per lane;
+// B fragments: per-tap weight slices staged in LDS, double buffered, fetched
+// into registers one tap ahead.  Activations in and out are BF16 (NHWC), the
+// LSTM cell state, every epilogue and the mixture parameters are FP32.
+#include "wv_internal.h"
+
+namespace wv {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TH = 16;
+constexpr int TW = 16;
+constexpr int HH = TH + 2;
+constexpr int HWD = TW + 2;
+constexpr int HALO = HH * HWD;
+
+__device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <int CIN, int NB, bool SYM, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
+    constexpr int STRIDE = CIN + 8;          // bf16 elements per halo position (conflict-free)
+    constexpr int CC = CIN / 32;             // 32-channel K chunks per tap
+    constexpr int BV = CC * NB * 64;         // uint4 of B per tap for this workgroup
+    constexpr int BPT = (BV + 255) / 256;
+    constexpr int MB = (MODE == CONV_HEAD) ? 2 : 4;   // head: only the rows of its step's parity
+    static_assert(BPT <= 2, "B slice too large");
+    // Input halo; after the MFMA loop it holds the output tile (RELU epilogue).
+    constexpr int LDS_IN = HALO * STRIDE > TH * TW * (NB * 16 + 8) ? HALO * STRIDE : TH * TW * (NB * 16 + 8);
+    __shared__ __attribute__((aligned(16))) uint16_t lds_in[LDS_IN];
+    __shared__ __attribute__((aligned(16))) uint4 lds_w[2][BV];
+    __shared__ __attribute__((aligned(16))) uint4 lds_ws[SYM ? NB * 64 : 1];
+    __shared__ uint16_t lds_s[SYM ? HALO : 1];
+    __shared__ float lds_head[MODE == CONV_HEAD ? 8 * TW * 17 : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int t = blockIdx.x;
+    const int tx = t % a.tiles_x;
+    t /= a.tiles_x;
+    const int ty = t % a.tiles_y;
+    const int n = t / a.tiles_y;
+    const int r0 = ty * TH;
+    const int c0 = tx * TW;
+    const int nblk0 = blockIdx.y * NB;
+    // Rows of this wave: 4w .. 4w+3; the head keeps the two of parity step/2.
+    const int gr = a.step >> 1;
+
+    const uint4* wg = reinterpret_cast<const uint4*>(L.w);
+    auto boff_of = [&](int k) -> long long {
+        const int idx = (tid + k * 256) < BV ? tid + k * 256 : 0;
+        const int cc = idx / (NB * 64);
+        const int rem = idx - cc * (NB * 64);
+        return ((long long)cc * L.nbt + nblk0 + (rem >> 6)) * 64 + (rem & 63);
+    };
+    const long long bo0 = boff_of(0);
+    const long long bo1 = BPT > 1 ? boff_of(1) : 0;
+    const long long btap = (long long)CC * L.nbt * 64;
+    uint4 b0, b1;
+#define WV_LOAD_B(tp)                                       \
+    {                                                       \
+        const uint4* wt_ = wg + (long long)(tp) * btap;     \
+        b0 = wt_[bo0];                                      \
+        if (BPT > 1) b1 = wt_[bo1];                         \
+    }
+#define WV_STORE_B(buf)                                                        \
+    {                                                                          \
+        if (BV >= 256 || tid < BV) lds_w[buf][tid] = b0;                       \
+        if (BPT > 1 && (BV >= 512 || tid + 256 < BV)) lds_w[buf][tid + 256] = b1; \
+    }
+    WV_LOAD_B(0)
+
+    {
+        const int win = a.w >> a.in_up;
+        const uint16_t* inp = a.in16 ? a.in16 + (long long)n * a.in_ps : nullptr;
+        constexpr int V = CIN / 8;   // uint4 per position
+        for (int idx = tid; idx < HALO * V; idx += 256) {
+            const int pos = idx / V;
+            const int c8 = idx - pos * V;
+            const int hy = pos / HWD;
+            const int hx = pos - hy * HWD;
+            const int r = r0 + hy - 1;
+            const int c = c0 + hx - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
+                v = *reinterpret_cast<const uint4*>(
+                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c8 * 8);
+            *reinterpret_cast<uint4*>(lds_in + pos * STRIDE + c8 * 8) = v;
+        }
+        if (SYM) {
+            const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
+            const int ws = a.w >> a.sym_up;
+            for (int pos = tid; pos < HALO; pos += 256) {
+                const int hy = pos / HWD;
+                const int hx = pos - hy * HWD;
+                const int r = r0 + hy - 1;
+                const int c = c0 + hx - 1;
+                float v = 0.f;
+                if (sp && r >= 0 && r < a.h && c >= 0 && c < a.w &&
+                    (2 * (r & 1) + (c & 1)) < a.sym_step)
+                    v = (float)sp[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
+                lds_s[pos] = f2bf(v);   // |symbol| <= 256 is exact in BF16
+            }
+            const uint4* wsg = reinterpret_cast<const uint4*>(L.wsym);
+            for (int idx = tid; idx < NB * 64; idx += 256)
+                lds_ws[idx] = wsg[(long long)nblk0 * 64 + idx];
+        }
+    }
+    WV_STORE_B(0)
+    __syncthreads();
+
+    floatx4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int m = lane & 15;
+    const int kk = lane >> 4;
+    // tile row of accumulator block mb
+    auto row_of = [&](int mb) { return MODE == CONV_HEAD ? wave * 4 + 2 * mb + gr : wave * 4 + mb; };
+
+    for (int tap = 0; tap < 9; ++tap) {
+        const int buf = tap & 1;
+        if (tap < 8) {
+            WV_LOAD_B(tap + 1)
+        }
+        const int dy = tap / 3;
+        const int dx = tap - dy * 3;
+#pragma unroll
+        for (int cc = 0; cc < CC; ++cc) {
+            uint4 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bv[nb] = lds_w[buf][(cc * NB + nb) * 64 + lane];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const uint4 av = *reinterpret_cast<const uint4*>(
+                    lds_in + ((row_of(mb) + dy) * HWD + m + dx) * STRIDE + cc * 32 + kk * 8);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(bv[nb]),
+                                                                          acc[mb][nb], 0, 0, 0);
+            }
+        }
+        if (tap < 8) {
+            WV_STORE_B(buf ^ 1)   // the other buffer was last read one tap ago
+            __syncthreads();
+        }
+    }
+#undef WV_LOAD_B
+#undef WV_STORE_B
+    if (SYM) {
+        // One K = 32 chunk: element j of lane group kk is tap 8 kk + j (taps >= 9 are zero).
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            uint16_t e[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int tap = kk * 8 + j;
+                e[j] = tap < 9 ? lds_s[(row_of(mb) + tap / 3) * HWD + m + tap % 3] : (uint16_t)0;
+            }
+            const uint4 av = make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
+                                        e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(lds_ws[nb * 64 + lane]),
+                                                                      acc[mb][nb], 0, 0, 0);
+        }
+    }
+
+    const int col = lane & 15;
+    const int rowq = (lane >> 4) * 4;
+    if (MODE == CONV_RELU || MODE == CONV_TANH) {
+        // Stage the output tile [256 positions][16 NB channels] in LDS (reusing the
+        // halo buffer), then write 16-byte chunks: full, coalesced lines.
+        constexpr int OS = NB * 16 + 8;
+        static_assert(TH * TW * OS <= LDS_IN, "output tile does not fit the halo buffer");
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float b = L.bias[(nblk0 + nb) * 16 + col];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[mb][nb][i] + b;
+                    v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
+                    lds_in[(row_of(mb) * TW + rowq + i) * OS + nb * 16 + col] = f2bf(v);
+                }
+            }
+        __syncthreads();
+        constexpr int V8 = NB * 2;   // 16-byte chunks per position
+        for (int idx = tid; idx < TH * TW * V8; idx += 256) {
+            const int pos = idx / V8;
+            const int c8 = idx - pos * V8;
+            const int r = r0 + pos / TW;
+            const int c = c0 + pos % TW;
+            if (r < a.h && c < a.w && (nblk0 * 16 + c8 * 8) < L.cout)
+                *reinterpret_cast<uint4*>(a.out16 + (long long)n * a.out_ps +
+                                          ((long long)r * a.w + c) * a.out_cs + nblk0 * 16 + c8 * 8) =
+                    *reinterpret_cast<const uint4*>(lds_in + pos * OS + c8 * 8);
+        }
+    } else if (MODE == CONV_LSTM) {
+        const int ch = blockIdx.y * 16 + col;
+        const float bi = L.bias[(nblk0 + 0) * 16 + col];
+        const float bf = L.bias[(nblk0 + 1) * 16 + col];
+        const float bg = L.bias[(nblk0 + 2) * 16 + col];
+        const float bo = L.bias[(nblk0 + 3) * 16 + col];
+        const int wp = a.w >> a.cprev_up;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = r0 + row_of(mb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = c0 + rowq + i;
+                if (r < a.h && c < a.w) {
+                    float cp = 0.f;
+                    if (a.c_prev)
+                        cp = a.c_prev[(long long)n * a.cprev_ps +
+                                      ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
+                    const float gi = sigmoidf_(acc[mb][0][i] + bi);
+                    const float gf = sigmoidf_(acc[mb][1][i] + bf);
+                    const float gg = tanhf(acc[mb][2][i] + bg);
+                    const float go = sigmoidf_(acc[mb][3][i] + bo);
+                    const float cn = gf * cp + gi * gg;
+                    const float hn = go * tanhf(cn);
+                    const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
+                    a.c_out[o] = cn;
+                    a.h16_out[o] = f2bf(hn);
+                }
+            }
+        }
+    } else {  // CONV_HEAD
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                lds_head[((wave * 2 + mb) * TW + rowq + i) * 17 + col] = acc[mb][0][i] + L.bias[col];
+        __syncthreads();
+        if (tid < 8 * TW) {
+            const int rr = tid / TW;                       // 0..7: wave rr/2, block rr%2
+            const int r = r0 + (rr >> 1) * 4 + 2 * (rr & 1) + gr;
+            const int c = c0 + tid % TW;
+            const int gc = a.step & 1;
+            if (r < a.h && c < a.w && (c & 1) == gc) {
+                const float* v = lds_head + tid * 17;
+                const int K = a.K;
+                const int wg2 = (a.w - gc + 1) >> 1;
+                const int hg = (a.h - gr + 1) >> 1;
+                const long long gi = (long long)(r >> 1) * wg2 + (c >> 1);
+                float* o = a.params + ((long long)n * hg * wg2 + gi) * 3 * K;
+                float mx = v[0];
+                for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
+                float e[4];
+                float se = 0.f;
+                for (int k = 0; k < K; ++k) {
+                    e[k] = __expf(v[k] - mx);
+                    se += e[k];
+                }
+                for (int k = 0; k < K; ++k) o[k] = e[k] / se;
+                for (int k = 0; k < K; ++k) o[K + k] = v[K + k];
+                for (int k = 0; k < K; ++k) {
+                    const float x = v[2 * K + k];
+                    const float sp = log1pf(__expf(-fabsf(x))) + fmaxf(x, 0.f);
+                    o[2 * K + k] = fmaxf(sp, a.sigma_min);
+                }
+            }
+        }
+    }
+}
+
+template <int CIN, int NB, bool SYM, int MODE>
+hipError_t launch_t(const MfmaLayer16& L, const ConvArgs& a0, hipStream_t s) {
+    ConvArgs a = a0;
+    a.tiles_x = (a.w + TW - 1) / TW;
+    a.tiles_y = (a.h + TH - 1) / TH;
+    const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
+    dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
+    hipLaunchKernelGGL((conv3x3_mfma_bf16<CIN, NB, SYM, MODE>), grid, dim3(256), 0, s, L, a);
+    return hipGetLastError();
+}
+
+template <int CIN, int NB, bool SYM>
+hipError_t dispatch_mode(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
+    switch (mode) {
+        case CONV_RELU: return launch_t<CIN, NB, SYM, CONV_RELU>(L, a, s);
+        case CONV_LSTM: return NB == 4 ? launch_t<CIN, 4, SYM, CONV_LSTM>(L, a, s) : hipErrorInvalidValue;
+        case CONV_HEAD: return NB == 1 ? launch_t<CIN, 1, SYM, CONV_HEAD>(L, a, s) : hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int CIN, int NB>
+hipError_t dispatch_sym(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
+    return L.has_sym ? dispatch_mode<CIN, NB, true>(L, mode, a, s)
+                     : dispatch_mode<CIN, NB, false>(L, mode, a, s);
+}
+
+inline int pick_nb(const MfmaLayer16& L, int mode, const ConvArgs& a) {
+    if (mode == CONV_HEAD) return 1;
+    if (mode == CONV_LSTM) return 4;
+    const long long tiles = (long long)((a.w + TW - 1) / TW) * ((a.h + TH - 1) / TH) * a.N;
+    int nb = L.nbt >= 4 ? 4 : L.nbt;
+    while (nb > 1 && tiles * (L.nbt / nb) < 512) nb >>= 1;
+    return nb;
+}
+
+template <int CIN>
+hipError_t dispatch_nb(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
+    switch (pick_nb(L, mode, a)) {
+        case 1: return dispatch_sym<CIN, 1>(L, mode, a, s);
+        case 2: return dispatch_sym<CIN, 2>(L, mode, a, s);
+        case 4: return dispatch_sym<CIN, 4>(L, mode, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
+    if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;
+    if (mode == CONV_LSTM && L.nbt % 4 != 0) return hipErrorInvalidValue;
+    switch (L.cin) {
+        case 32: return dispatch_nb<32>(L, mode, a, s);
+        case 64: return dispatch_nb<64>(L, mode, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace wv

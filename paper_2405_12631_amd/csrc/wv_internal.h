@@ -46,6 +46,15 @@ struct MfmaLayer {
     int has_sym;   // 1: extra input channel 0 read from int16 symbols
 };
 
+// BF16 variant: w [9][cin/32][nbt][64 lanes][8 bf16], wsym [nbt][64 lanes][8 bf16]
+// (element j of lane group kk is tap 8 kk + j), bias FP32 [nbt * 16].
+struct MfmaLayer16 {
+    const uint16_t* w;
+    const uint16_t* wsym;
+    const float* bias;
+    int cin, cout, nbt, has_sym;
+};
+
 // A 1 -> C or C -> 1 lifting conv for the vector kernels: w [9][C], bias [C] / [1].
 struct VecLayer {
     const float* w;
@@ -73,6 +82,10 @@ struct ConvArgs {
     float* c_out;
     long long st_ps;
     int C;
+    // BF16 kernels: activations / hidden state in BF16 (same strides, in elements)
+    const uint16_t* in16;
+    uint16_t* out16;
+    uint16_t* h16_out;
     // CONV_HEAD
     float* params;         // [N][n_g][3K]
     int step, K;
@@ -81,6 +94,7 @@ struct ConvArgs {
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s);
+hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s);
 
 // Lifting filter pieces.
 //   first: a1[n][r][c][ch] = tanh(b[ch] + sum_tap w[tap][ch] z(n, r+dy-1, c+dx-1))

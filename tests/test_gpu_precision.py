@@ -1,0 +1,77 @@
+"""BF16 context convs: error against the FP64 oracle, bit-exact GPU round trip,
+batch invariance (needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes, gradient_noise_image
+from gpu_common import need_gpu, q_to_device, say, check_cdf_rows, TAU
+
+pytestmark = pytest.mark.gpu
+
+# No parity bar is set for reduced precision; these bounds only catch a broken
+# kernel (an FP32-accumulated BF16 conv stack stays far inside them).
+BF16_MEAN_REL = 2e-2
+BF16_MAX_ABS_W = 0.1
+
+
+def _errs(gpu, ref, K):
+    g = np.asarray(gpu, np.float64).reshape(-1, 3 * K)
+    r = np.asarray(ref, np.float64).reshape(-1, 3 * K)
+    den = np.abs(r)
+    den[:, :2 * K] = np.maximum(den[:, :2 * K], TAU)
+    rel = np.abs(g - r) / den
+    return rel, np.abs(g[:, :K] - r[:, :K]).max(initial=0)
+
+
+@pytest.mark.parametrize("name,H,W,N", [("gray64", 64, 64, 1), ("ycbcr512x768", 64, 96, 3)])
+def test_bf16_params_against_oracle(name, H, W, N):
+    need_gpu()
+    from paper_2405_12631_amd import codec, WV_BF16
+    say("bf16 params", name)
+    cfg = get_config(name)
+    w = make_weights(cfg)
+    model = codec.Model(cfg, pack_weights(cfg, w), precision=WV_BF16)
+    x = gradient_noise_image(H, W, seed=1)[None] if N == 1 else sinusoid_1f_planes(H, W, planes=N, seed=2)
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    ws = codec.Workspace(model, N, H, W)
+    got = codec.params_all(model, q_to_device(qs), ws)
+    ref = O.context_params_all(qs, cfg, w)
+    rels, wmax = [], 0.0
+    for i in range(len(ref)):
+        for g in range(4):
+            r, wm = _errs(got[i][g].cpu().numpy(), ref[i][g], cfg["mix_k"])
+            rels.append(r.ravel())
+            wmax = max(wmax, wm)
+    rel = np.concatenate(rels)
+    say(f"bf16 {name}: mean rel {rel.mean():.3e} median {np.median(rel):.3e} max {rel.max():.3e} "
+        f"max |dw| {wmax:.3e}")
+    assert rel.mean() < BF16_MEAN_REL and wmax < BF16_MAX_ABS_W
+    for i in (0, len(ref) - 1):
+        cdf = codec.cdf_tables(model, got[i][3])
+        check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[i][3].cpu().numpy(), cfg)
+
+
+def test_bf16_roundtrip_bit_exact_and_batch_invariant():
+    need_gpu()
+    from paper_2405_12631_amd import codec, WV_BF16
+    say("bf16 roundtrip")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=3)
+    data, q_enc = codec.encode(model, x)
+    _, _, q_dec = codec.decode(model, data)
+    assert torch.equal(q_enc, q_dec)
+    ws3 = codec.Workspace(model, 3, 64, 96)
+    ws1 = codec.Workspace(model, 1, 64, 96)
+    p3 = codec.params_all(model, q_enc, ws3)
+    p1 = codec.params_all(model, q_enc[2:3].contiguous(), ws1)
+    for i in range(13):
+        for g in range(4):
+            assert torch.equal(p3[i][g][2:3], p1[i][g])
+    # A stream written by the FP32 model is refused by the BF16 model.
+    fp32 = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)))
+    d32, _ = codec.encode(fp32, x[:1])
+    with pytest.raises(Exception):
+        codec.decode(model, d32)
