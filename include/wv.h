@@ -70,6 +70,8 @@ typedef struct wv_config {
     float sigma_min; /* lower bound of the mixture scales, symbol units        */
     int lift_int;    /* 1: predict/update outputs rounded (lossless lifting)   */
     int dist;        /* wv_dist: mixture component family                     */
+    int ctx_arch;    /* 0: plain conv stacks; 1: DepthConvBlock (step 0) and
+                        Residual Block (steps 1-3) stacks, Sec. 3.2 (FP32 only) */
 } wv_config;
 
 /* One subband of the packed layout. type: 0 LL, 1 HL, 2 LH, 3 HH. */
@@ -94,6 +96,10 @@ int wv_version(void);
  *       ctx_layers convs each: Cin_g -> ctx_ch, ctx_ch -> ctx_ch
  *       (ctx_layers - 2 times), ctx_ch -> 3K; Cin_0 = ctx_ch, Cin_g = 1 + ctx_ch
  *       for g >= 1 with channel 0 the current subband's coded symbols.
+ *   With ctx_arch = 1 each stack is instead: in (3x3, Cin_g -> C); step 0 a
+ *       DepthConvBlock p1a (1x1 [C][C][1][1]), dw (depth-wise [C][1][3][3]),
+ *       p1b, p2a, p2b (1x1); steps 1-3 a Residual Block ra, rb (3x3 C -> C);
+ *       out (3x3, C -> 3K).
  * wv_weights_count: number of floats of that blob for cfg.
  */
 int wv_weights_count(const wv_config* cfg, long long* n_floats);

@@ -333,6 +333,55 @@ def step_stack(z, convs):
     return a
 
 
+def conv1x1(x, w, b):
+    """Pointwise conv: out[..., o] = b[o] + sum_i w[o, i, 0, 0] x[..., i]."""
+    return np.asarray(x, np.float64) @ np.asarray(w, np.float64)[:, :, 0, 0].T + np.asarray(b, np.float64)
+
+
+def dwconv3x3(x, w, b):
+    """Depth-wise 3x3 conv, one group per channel (Sec. 3.2: each input channel is
+    convolved with its own kernel): out[n,r,c,ch] = b[ch] + sum_tap w[ch,0,tap] x[n,r+dy-1,c+dx-1,ch]."""
+    x = np.asarray(x, np.float64)
+    w = np.asarray(w, np.float64)
+    N, H, W, C = x.shape
+    xp = np.pad(x, ((0, 0), (1, 1), (1, 1), (0, 0)))
+    out = np.empty_like(x)
+    out[...] = np.asarray(b, np.float64)
+    for dy in range(3):
+        for dx in range(3):
+            out += xp[:, dy:dy + H, dx:dx + W, :] * w[:, 0, dy, dx]
+    return out
+
+
+def _wb(weights, name):
+    return np.asarray(weights[name + ".w"], np.float64), np.asarray(weights[name + ".b"], np.float64)
+
+
+def depth_conv_block(x, weights, pre):
+    """DepthConvBlock (Sec. 3.2, Fig. 5): a two-part residual block whose first part holds a
+    depth-wise conv.  Reading (the figure is not in the text): part 1
+    x + 1x1(dw3x3(relu(1x1(x)))), part 2 x + 1x1(relu(1x1(x)))."""
+    t = np.maximum(conv1x1(x, *_wb(weights, pre + ".p1a")), 0.0)
+    t = dwconv3x3(t, *_wb(weights, pre + ".dw"))
+    x = x + conv1x1(t, *_wb(weights, pre + ".p1b"))
+    t = np.maximum(conv1x1(x, *_wb(weights, pre + ".p2a")), 0.0)
+    return x + conv1x1(t, *_wb(weights, pre + ".p2b"))
+
+
+def residual_block(x, weights, pre):
+    """Two-layer Residual Block (Sec. 3.2): x + conv3x3(relu(conv3x3(x)))."""
+    t = np.maximum(conv3x3(x, *_wb(weights, pre + ".ra")), 0.0)
+    return x + conv3x3(t, *_wb(weights, pre + ".rb"))
+
+
+def step_stack_blocks(z, weights, pre, g):
+    """Step stack of the block architecture: conv3x3 in, ReLU, the step's block
+    (DepthConvBlock for step 0, Residual Block otherwise, Sec. 3.2), conv3x3 out."""
+    a = np.maximum(conv3x3(z, *_wb(weights, pre + ".in")), 0.0)
+    a = depth_conv_block(a, weights, pre) if g == 0 else residual_block(a, weights, pre)
+    return conv3x3(a, *_wb(weights, pre + ".out"))
+
+
 def softplus(v):
     return np.log1p(np.exp(-np.abs(v))) + np.maximum(v, 0.0)
 
@@ -364,8 +413,11 @@ def group_positions(h, w, g):
 
 def step_params(q_i, l_i, t, g, cfg, weights):
     """Entropy parameters [N][n_g][3K] of coding step g of a subband of type t (Sec. 3.2)."""
-    convs = _convs(weights, f"ctx.{TYPE_NAMES[t]}.{g}", cfg["ctx_layers"])
-    r = step_stack(step_input(q_i, l_i, g), convs)
+    pre = f"ctx.{TYPE_NAMES[t]}.{g}"
+    if cfg.get("ctx_arch", "plain") == "blocks":
+        r = step_stack_blocks(step_input(q_i, l_i, g), weights, pre, g)
+    else:
+        r = step_stack(step_input(q_i, l_i, g), _convs(weights, pre, cfg["ctx_layers"]))
     rr, cc = group_positions(q_i.shape[1], q_i.shape[2], g)
     return mixture_head(r[:, rr, cc, :], cfg)
 

@@ -31,7 +31,8 @@ class wv_config(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("lift_ch", ctypes.c_int), ("lift_layers", ctypes.c_int),
                 ("ctx_ch", ctypes.c_int), ("ctx_layers", ctypes.c_int), ("mix_k", ctypes.c_int),
                 ("sym_min", ctypes.c_int), ("sym_max", ctypes.c_int), ("cdf_bits", ctypes.c_int),
-                ("sigma_min", ctypes.c_float), ("lift_int", ctypes.c_int), ("dist", ctypes.c_int)]
+                ("sigma_min", ctypes.c_float), ("lift_int", ctypes.c_int), ("dist", ctypes.c_int),
+                ("ctx_arch", ctypes.c_int)]
 
 
 class wv_subband(ctypes.Structure):

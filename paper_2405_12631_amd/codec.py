@@ -25,7 +25,8 @@ def make_config(cfg):
                        ctx_ch=cfg["ctx_ch"], ctx_layers=cfg["ctx_layers"], mix_k=cfg["mix_k"],
                        sym_min=cfg["sym_min"], sym_max=cfg["sym_max"], cdf_bits=cfg["cdf_bits"],
                        sigma_min=cfg["sigma_min"], lift_int=int(cfg.get("lift_int", 0)),
-                       dist=L.DISTS[cfg.get("dist", "gauss")])
+                       dist=L.DISTS[cfg.get("dist", "gauss")],
+                       ctx_arch=1 if cfg.get("ctx_arch", "plain") == "blocks" else 0)
 
 
 def _ptr(t):

@@ -55,6 +55,7 @@ static int check_cfg(const wv_config* c) {
     if (c->cdf_bits != 16) return fail(WV_EUNSUPPORTED, "cdf_bits must be 16");
     if (!(c->sigma_min > 0.f)) return fail(WV_EINVAL, "sigma_min must be > 0");
     if (c->dist != WV_DIST_GAUSS && c->dist != WV_DIST_LAPLACE) return fail(WV_EINVAL, "bad dist");
+    if (c->ctx_arch != 0 && c->ctx_arch != 1) return fail(WV_EINVAL, "bad ctx_arch");
     return WV_OK;
 }
 
@@ -63,21 +64,28 @@ namespace {
 struct ConvShape {
     int cin, cout;
     long long w_off, b_off;   // float offsets in the blob
+    int ks2 = 9;              // taps per filter (9 for 3x3, 1 for 1x1)
+};
+
+// Block architecture of one (type, step) stack, in blob order.
+struct BlockShapes {
+    ConvShape in, p1a, dw, p1b, p2a, p2b, ra, rb, out;   // dw: depth-wise [C][1][3][3]
 };
 
 struct Manifest {
     std::vector<ConvShape> lift[4];   // P_row, U_row, P_col, U_col
     ConvShape lstm;
-    std::vector<ConvShape> ctx[4][4]; // [type][step]
+    std::vector<ConvShape> ctx[4][4]; // [type][step], plain stacks
+    BlockShapes blk[4][4];            // [type][step], ctx_arch == 1
     long long total = 0;
 };
 
 Manifest make_manifest(const wv_config& c) {
     Manifest m;
     long long off = 0;
-    auto conv = [&](int cin, int cout) {
-        ConvShape s{cin, cout, off, 0};
-        off += (long long)cout * cin * 9;
+    auto conv = [&](int cin, int cout, int ks2 = 9) {
+        ConvShape s{cin, cout, off, 0, ks2};
+        off += (long long)cout * cin * ks2;
         s.b_off = off;
         off += cout;
         return s;
@@ -90,8 +98,25 @@ Manifest make_manifest(const wv_config& c) {
         for (size_t l = 0; l + 1 < ch.size(); ++l) m.lift[f].push_back(conv(ch[l], ch[l + 1]));
     }
     m.lstm = conv(1 + c.ctx_ch, 4 * c.ctx_ch);
+    const int C = c.ctx_ch;
     for (int t = 0; t < 4; ++t)
         for (int g = 0; g < 4; ++g) {
+            if (c.ctx_arch == 1) {
+                BlockShapes& b = m.blk[t][g];
+                b.in = conv(g == 0 ? C : C + 1, C);
+                if (g == 0) {
+                    b.p1a = conv(C, C, 1);
+                    b.dw = conv(1, C);   // [C][1][3][3]
+                    b.p1b = conv(C, C, 1);
+                    b.p2a = conv(C, C, 1);
+                    b.p2b = conv(C, C, 1);
+                } else {
+                    b.ra = conv(C, C);
+                    b.rb = conv(C, C);
+                }
+                b.out = conv(C, 3 * c.mix_k);
+                continue;
+            }
             std::vector<int> ch;
             ch.push_back(g == 0 ? c.ctx_ch : 1 + c.ctx_ch);
             for (int l = 0; l < c.ctx_layers - 1; ++l) ch.push_back(c.ctx_ch);
@@ -112,7 +137,7 @@ struct PackBuf {
     }
 };
 
-struct MfmaRef { size_t w, wsym, bias; int cin, cout, nbt, has_sym; };
+struct MfmaRef { size_t w, wsym, bias; int cin, cout, nbt, has_sym, taps; };
 struct VecRef { size_t w, bias; int ch; };
 
 // Original output channel of packed column nc.  LSTM: columns are grouped by
@@ -131,15 +156,17 @@ MfmaRef pack_mfma(PackBuf& pb, const float* blob, const ConvShape& s, int has_sy
     r.cout = s.cout;
     r.nbt = (s.cout + 15) / 16;
     r.has_sym = has_sym;
+    r.taps = s.ks2;
     const int CB = r.cin / 16;
     const int cin_total = s.cin;
+    const int KS2 = s.ks2;
     const float* W = blob + s.w_off;
     const float* B = blob + s.b_off;
-    r.w = pb.add((size_t)9 * CB * r.nbt * 256);
+    r.w = pb.add((size_t)KS2 * CB * r.nbt * 256);
     r.wsym = has_sym ? pb.add((size_t)3 * r.nbt * 64) : 0;
     r.bias = pb.add((size_t)r.nbt * 16);
     float* pw = pb.data.data() + r.w;
-    for (int tap = 0; tap < 9; ++tap)
+    for (int tap = 0; tap < KS2; ++tap)
         for (int cb = 0; cb < CB; ++cb)
             for (int nb = 0; nb < r.nbt; ++nb)
                 for (int lane = 0; lane < 64; ++lane)
@@ -150,7 +177,7 @@ MfmaRef pack_mfma(PackBuf& pb, const float* blob, const ConvShape& s, int has_sy
                         float v = 0.f;
                         if (nc < s.cout) {
                             const int o = perm_col(nc, C, lstm);
-                            v = W[((long long)o * cin_total + has_sym + k) * 9 + tap];
+                            v = W[((long long)o * cin_total + has_sym + k) * KS2 + tap];
                         }
                         pw[(((size_t)(tap * CB + cb) * r.nbt + nb) * 64 + lane) * 4 + t] = v;
                     }
@@ -189,6 +216,7 @@ MfmaRef pack_mfma16(PackBuf& pb, const float* blob, const ConvShape& s, int has_
     r.cout = s.cout;
     r.nbt = (s.cout + 15) / 16;
     r.has_sym = has_sym;
+    r.taps = 9;
     const int CC = r.cin / 32;
     const int cin_total = s.cin;
     const float* W = blob + s.w_off;
@@ -253,11 +281,17 @@ VecRef pack_vec_last(PackBuf& pb, const float* blob, const ConvShape& s) {
     return r;
 }
 
+struct BlockRefs {
+    MfmaRef in, p1a, p1b, p2a, p2b, ra, rb, out;
+    size_t dw_w, dw_b;   // depth-wise [9][C], [C]
+};
+
 struct HostModel {
     VecRef lift_first[4], lift_last[4];
     std::vector<MfmaRef> lift_mid[4];
     MfmaRef lstm;
     std::vector<MfmaRef> ctx[4][4];
+    BlockRefs blk[4][4];
 };
 
 // Context layers are packed for the precision's kernel; lifting is always FP32.
@@ -275,6 +309,29 @@ HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c, int preci
     hm.lstm = ctxpack(pb, blob, mf.lstm, 1, true, c.ctx_ch);
     for (int t = 0; t < 4; ++t)
         for (int g = 0; g < 4; ++g) {
+            if (c.ctx_arch == 1) {
+                const BlockShapes& b = mf.blk[t][g];
+                BlockRefs& r = hm.blk[t][g];
+                r.in = pack_mfma(pb, blob, b.in, g > 0 ? 1 : 0, false, 0);
+                if (g == 0) {
+                    r.p1a = pack_mfma(pb, blob, b.p1a, 0, false, 0);
+                    r.p1b = pack_mfma(pb, blob, b.p1b, 0, false, 0);
+                    r.p2a = pack_mfma(pb, blob, b.p2a, 0, false, 0);
+                    r.p2b = pack_mfma(pb, blob, b.p2b, 0, false, 0);
+                    const int C = c.ctx_ch;
+                    r.dw_w = pb.add((size_t)9 * C);
+                    r.dw_b = pb.add((size_t)C);
+                    for (int tap = 0; tap < 9; ++tap)
+                        for (int ch = 0; ch < C; ++ch)
+                            pb.data[r.dw_w + tap * C + ch] = blob[b.dw.w_off + (long long)ch * 9 + tap];
+                    for (int ch = 0; ch < C; ++ch) pb.data[r.dw_b + ch] = blob[b.dw.b_off + ch];
+                } else {
+                    r.ra = pack_mfma(pb, blob, b.ra, 0, false, 0);
+                    r.rb = pack_mfma(pb, blob, b.rb, 0, false, 0);
+                }
+                r.out = pack_mfma(pb, blob, b.out, 0, false, 0);
+                continue;
+            }
             const auto& v = mf.ctx[t][g];
             for (size_t l = 0; l < v.size(); ++l)
                 hm.ctx[t][g].push_back(ctxpack(pb, blob, v[l], (l == 0 && g > 0) ? 1 : 0, false, 0));
@@ -293,12 +350,18 @@ struct wv_model {
     std::vector<MfmaLayer> ctx[4][4];
     MfmaLayer16 lstm16;                  // WV_BF16
     std::vector<MfmaLayer16> ctx16[4][4];
+    struct Blocks {                      // ctx_arch == 1
+        MfmaLayer in, p1a, p1b, p2a, p2b, ra, rb, out;
+        const float* dw_w;
+        const float* dw_b;
+    } blk[4][4];
 };
 
 static int check_precision(const wv_config* c, int precision) {
     if (precision == WV_FP32) return WV_OK;
     if (precision == WV_BF16) {
         if (c->ctx_ch % 32) return fail(WV_EUNSUPPORTED, "BF16 context needs ctx_ch of 32 or 64");
+        if (c->ctx_arch != 0) return fail(WV_EUNSUPPORTED, "BF16 context needs ctx_arch 0");
         return WV_OK;
     }
     return fail(WV_EUNSUPPORTED, "precision %d is not implemented", precision);
@@ -356,7 +419,7 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
     const float* base = (const float*)d_pack;
     auto mfma = [&](const MfmaRef& r) {
         return MfmaLayer{base + r.w, r.has_sym ? base + r.wsym : nullptr, base + r.bias,
-                         r.cin, r.cout, r.nbt, r.has_sym};
+                         r.cin, r.cout, r.nbt, r.has_sym, r.taps};
     };
     auto vec = [&](const VecRef& r) { return VecLayer{base + r.w, base + r.bias, r.ch}; };
     auto mfma16 = [&](const MfmaRef& r) {
@@ -380,8 +443,26 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
     } else {
         m->lstm = mfma(hm.lstm);
         for (int t = 0; t < 4; ++t)
-            for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < 4; ++g) {
                 for (auto& r : hm.ctx[t][g]) m->ctx[t][g].push_back(mfma(r));
+                if (cfg->ctx_arch == 1) {
+                    const BlockRefs& r = hm.blk[t][g];
+                    wv_model::Blocks& b = m->blk[t][g];
+                    b.in = mfma(r.in);
+                    b.out = mfma(r.out);
+                    if (g == 0) {
+                        b.p1a = mfma(r.p1a);
+                        b.p1b = mfma(r.p1b);
+                        b.p2a = mfma(r.p2a);
+                        b.p2b = mfma(r.p2b);
+                        b.dw_w = base + r.dw_w;
+                        b.dw_b = base + r.dw_b;
+                    } else {
+                        b.ra = mfma(r.ra);
+                        b.rb = mfma(r.rb);
+                    }
+                }
+            }
     }
     *out = m;
     return WV_OK;
@@ -420,7 +501,7 @@ int layout(const wv_config& c, int H, int W, std::vector<Sub>& out) {
 // Float offsets of the per-call scratch regions (all 256-byte aligned).
 struct Scratch {
     size_t X0, Xa, Xb, lbuf, hbuf, y, a1, a2;   // lifting
-    size_t act0, act1;                          // context
+    size_t act0, act1, act2;                    // context
     size_t total;
 };
 
@@ -445,6 +526,7 @@ Scratch scratch_layout(const wv_config& c, int N, int H, int W) {
     const size_t act = (size_t)N * (H / 2) * (W / 2) * c.ctx_ch;
     s.act0 = o; o = al(o + act);
     s.act1 = o; o = al(o + act);
+    s.act2 = o; o = al(o + act);
     s.total = (lift_total > o ? lift_total : o) * sizeof(float);
     return s;
 }
@@ -793,7 +875,50 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
     }
     float* base = (float*)d_scratch;
     const Scratch sc = scratch_layout(m->cfg, N, H, W);
-    float* act[2] = {base + sc.act0, base + sc.act1};
+    float* act[3] = {base + sc.act0, base + sc.act1, base + sc.act2};
+    if (m->cfg.ctx_arch == 1) {
+        // in -> block -> out (Sec. 3.2): step 0 a DepthConvBlock, steps 1-3 a Residual Block.
+        const wv_model::Blocks& b = m->blk[S.type][g];
+        auto run = [&](const MfmaLayer& L, int mode, const float* in, float* out,
+                       const float* skip) -> int {
+            ConvArgs a{};
+            a.in = in;
+            a.in_ps = st_ps;
+            a.N = N;
+            a.h = S.h;
+            a.w = S.w;
+            a.tiles_x = (S.w + TILE_W - 1) / TILE_W;
+            a.tiles_y = (S.h + TILE_H - 1) / TILE_H;
+            if (L.has_sym) {
+                a.sym = d_q + S.off;
+                a.sym_ps = HW;
+                a.sym_step = g;
+            }
+            a.out = out;
+            a.out_ps = st_ps;
+            a.out_cs = C;
+            a.skip = skip;
+            a.params = d_params;
+            a.step = g;
+            a.K = m->cfg.mix_k;
+            a.sigma_min = m->cfg.sigma_min;
+            HIPCHK(launch_conv(L, mode, a, s));
+            return WV_OK;
+        };
+        int rc2;
+        if ((rc2 = run(b.in, CONV_RELU, hcur, act[0], nullptr))) return rc2;
+        if (g == 0) {
+            if ((rc2 = run(b.p1a, CONV_RELU, act[0], act[1], nullptr))) return rc2;
+            HIPCHK(launch_dwconv(act[1], b.dw_w, b.dw_b, act[2], N, S.h, S.w, C, s));
+            if ((rc2 = run(b.p1b, CONV_RES, act[2], act[1], act[0]))) return rc2;
+            if ((rc2 = run(b.p2a, CONV_RELU, act[1], act[0], nullptr))) return rc2;
+            if ((rc2 = run(b.p2b, CONV_RES, act[0], act[2], act[1]))) return rc2;
+        } else {
+            if ((rc2 = run(b.ra, CONV_RELU, act[0], act[1], nullptr))) return rc2;
+            if ((rc2 = run(b.rb, CONV_RES, act[1], act[2], act[0]))) return rc2;
+        }
+        return run(b.out, CONV_HEAD, act[2], nullptr, nullptr);
+    }
     const size_t nlayers = bf16 ? m->ctx16[S.type][g].size() : m->ctx[S.type][g].size();
     const float* in = hcur;
     for (size_t l = 0; l < nlayers; ++l) {

@@ -30,8 +30,9 @@ constexpr int HALO = HALO_H * HALO_W;
 
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
 
-template <int CIN, int NB, bool SYM, int MODE>
+template <int CIN, int NB, bool SYM, int MODE, int TAPS>
 __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
+    // TAPS == 9: 3x3 conv; TAPS == 1: 1x1 conv (centre tap only, same data path).
     constexpr int STRIDE = CIN + 4;          // 68 floats for CIN = 64: conflict-free float4 reads
     constexpr int CB = CIN / 16;
     constexpr int BV4 = CB * NB * 64;        // float4 of B per tap for this workgroup's N blocks
@@ -145,12 +146,12 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     const int m = lane & 15;
     const int kk = lane >> 4;
 
-    for (int tap = 0; tap < 9; ++tap) {
-        if (tap < 8) {
+    for (int tap = 0; tap < TAPS; ++tap) {
+        if (tap < TAPS - 1) {
             WV_LOAD_B(tap + 1)   // in flight while this tap computes
         }
-        const int dy = tap / 3;
-        const int dx = tap - dy * 3;
+        const int dy = TAPS == 1 ? 1 : tap / 3;
+        const int dx = TAPS == 1 ? 1 : tap - dy * 3;
         const float* arow0 = lds_in + ((row0 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                                                                        acc[mb][nb], 0, 0, 0);
                 }
         }
-        if (tap < 8) {
+        if (tap < TAPS - 1) {
             __syncthreads();   // every wave is done with this tap's B
             WV_STORE_B()
             __syncthreads();
@@ -208,9 +209,10 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     // ---- epilogues.  Lane holds D[4*(lane/16) + i][lane % 16] of each block. ----
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
-    if (MODE == CONV_RELU || MODE == CONV_TANH) {
+    if (MODE == CONV_RELU || MODE == CONV_TANH || MODE == CONV_RES) {
         // Stage the output tile [128 positions][16 NB channels] in LDS (reusing the
-        // halo buffer), then write float4 chunks: full, coalesced lines.
+        // halo buffer), then write float4 chunks: full, coalesced lines.  CONV_RES
+        // adds the skip tensor (same layout as the output) while storing.
         constexpr int OS = NB * 16 + 4;
         static_assert(TILE_H * TILE_W * OS <= LDS_IN, "output tile does not fit the halo buffer");
         __syncthreads();
@@ -222,7 +224,8 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[mb][nb][i] + b;
-                    v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
+                    if (MODE == CONV_RELU) v = fmaxf(v, 0.f);
+                    if (MODE == CONV_TANH) v = tanhf(v);
                     lds_in[((row0 + mb) * TILE_W + rowq + i) * OS + nb * 16 + col] = v;
                 }
             }
@@ -233,10 +236,16 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
             const int c4 = idx - pos * V4;
             const int r = r0 + pos / TILE_W;
             const int c = c0 + pos % TILE_W;
-            if (r < a.h && c < a.w && (nblk0 * 16 + c4 * 4) < L.cout)
-                *reinterpret_cast<float4*>(a.out + (long long)n * a.out_ps +
-                                           ((long long)r * a.w + c) * a.out_cs + nblk0 * 16 + c4 * 4) =
-                    *reinterpret_cast<const float4*>(lds_in + pos * OS + c4 * 4);
+            if (r < a.h && c < a.w && (nblk0 * 16 + c4 * 4) < L.cout) {
+                const long long o = (long long)n * a.out_ps + ((long long)r * a.w + c) * a.out_cs +
+                                    nblk0 * 16 + c4 * 4;
+                float4 v = *reinterpret_cast<const float4*>(lds_in + pos * OS + c4 * 4);
+                if (MODE == CONV_RES) {
+                    const float4 k = *reinterpret_cast<const float4*>(a.skip + o);
+                    v = make_float4(v.x + k.x, v.y + k.y, v.z + k.z, v.w + k.w);
+                }
+                *reinterpret_cast<float4*>(a.out + o) = v;
+            }
         }
     } else if (MODE == CONV_LSTM) {
         // Block nb of this workgroup is gate nb (input, forget, cell, output)
@@ -308,19 +317,28 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     }
 }
 
-template <int CIN, int NB, bool SYM, int MODE>
+template <int CIN, int NB, bool SYM, int MODE, int TAPS = 9>
 hipError_t launch_t(const MfmaLayer& L, const ConvArgs& a, hipStream_t s) {
     const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
     dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
-    hipLaunchKernelGGL((conv3x3_mfma_f32<CIN, NB, SYM, MODE>), grid, dim3(256), 0, s, L, a);
+    hipLaunchKernelGGL((conv3x3_mfma_f32<CIN, NB, SYM, MODE, TAPS>), grid, dim3(256), 0, s, L, a);
     return hipGetLastError();
 }
 
 template <int CIN, int NB, bool SYM>
-hipError_t dispatch_mode(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+hipError_t dispatch_mode(const MfmaLayer& L, int mode, int taps, const ConvArgs& a, hipStream_t s) {
+    if (taps == 1) {
+        if (SYM) return hipErrorInvalidValue;
+        switch (mode) {
+            case CONV_RELU: return launch_t<CIN, NB, false, CONV_RELU, 1>(L, a, s);
+            case CONV_RES: return launch_t<CIN, NB, false, CONV_RES, 1>(L, a, s);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (mode) {
         case CONV_RELU: return launch_t<CIN, NB, SYM, CONV_RELU>(L, a, s);
         case CONV_TANH: return launch_t<CIN, NB, SYM, CONV_TANH>(L, a, s);
+        case CONV_RES: return SYM ? hipErrorInvalidValue : launch_t<CIN, NB, false, CONV_RES>(L, a, s);
         case CONV_LSTM: return NB == 4 ? launch_t<CIN, 4, SYM, CONV_LSTM>(L, a, s) : hipErrorInvalidValue;
         case CONV_HEAD: return NB == 1 ? launch_t<CIN, 1, SYM, CONV_HEAD>(L, a, s) : hipErrorInvalidValue;
     }
@@ -328,9 +346,9 @@ hipError_t dispatch_mode(const MfmaLayer& L, int mode, const ConvArgs& a, hipStr
 }
 
 template <int CIN, int NB>
-hipError_t dispatch_sym(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
-    return L.has_sym ? dispatch_mode<CIN, NB, true>(L, mode, a, s)
-                     : dispatch_mode<CIN, NB, false>(L, mode, a, s);
+hipError_t dispatch_sym(const MfmaLayer& L, int mode, int taps, const ConvArgs& a, hipStream_t s) {
+    return L.has_sym ? dispatch_mode<CIN, NB, true>(L, mode, taps, a, s)
+                     : dispatch_mode<CIN, NB, false>(L, mode, taps, a, s);
 }
 
 // Output blocks per workgroup.  Small subbands give few position tiles; there
@@ -346,12 +364,12 @@ inline int pick_nb(const MfmaLayer& L, int mode, const ConvArgs& a) {
 }
 
 template <int CIN>
-hipError_t dispatch_nb(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
+hipError_t dispatch_nb(const MfmaLayer& L, int mode, int taps, const ConvArgs& a, hipStream_t s) {
     const int nb = pick_nb(L, mode, a);
     switch (nb) {
-        case 1: return dispatch_sym<CIN, 1>(L, mode, a, s);
-        case 2: return dispatch_sym<CIN, 2>(L, mode, a, s);
-        case 4: return dispatch_sym<CIN, 4>(L, mode, a, s);
+        case 1: return dispatch_sym<CIN, 1>(L, mode, taps, a, s);
+        case 2: return dispatch_sym<CIN, 2>(L, mode, taps, a, s);
+        case 4: return dispatch_sym<CIN, 4>(L, mode, taps, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -360,13 +378,12 @@ hipError_t dispatch_nb(const MfmaLayer& L, int mode, const ConvArgs& a, hipStrea
 
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
     if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;
-    if (mode != CONV_HEAD && mode != CONV_LSTM && (L.nbt % (L.nbt >= 4 ? 4 : L.nbt)) != 0)
-        return hipErrorInvalidValue;
     if (mode == CONV_LSTM && L.nbt % 4 != 0) return hipErrorInvalidValue;
+    const int taps = L.taps == 1 ? 1 : 9;
     switch (L.cin) {
-        case 16: return dispatch_nb<16>(L, mode, a, s);
-        case 32: return dispatch_nb<32>(L, mode, a, s);
-        case 64: return dispatch_nb<64>(L, mode, a, s);
+        case 16: return dispatch_nb<16>(L, mode, taps, a, s);
+        case 32: return dispatch_nb<32>(L, mode, taps, a, s);
+        case 64: return dispatch_nb<64>(L, mode, taps, a, s);
     }
     return hipErrorInvalidValue;
 }

@@ -30,7 +30,8 @@ constexpr int TILE_H = 8;
 constexpr int TILE_W = 16;
 
 // Epilogue of the MFMA conv kernel.
-enum ConvMode { CONV_RELU = 0, CONV_TANH = 1, CONV_LSTM = 2, CONV_HEAD = 3 };
+// CONV_RES: out = skip + (conv + bias), no activation (residual blocks).
+enum ConvMode { CONV_RELU = 0, CONV_TANH = 1, CONV_LSTM = 2, CONV_HEAD = 3, CONV_RES = 4 };
 
 // One conv3x3 layer repacked for the MFMA kernel (see pack_mfma_layer):
 //   w    : [9][cin/16][nbt][64 lanes][4]  float B fragments
@@ -44,6 +45,7 @@ struct MfmaLayer {
     int cout;      // real output channels
     int nbt;       // output blocks of 16 (padded)
     int has_sym;   // 1: extra input channel 0 read from int16 symbols
+    int taps;      // 9: 3x3 conv (w holds 9 taps); 1: 1x1 conv
 };
 
 // BF16 variant: w [9][cin/32][nbt][64 lanes][8 bf16], wsym [nbt][64 lanes][8 bf16]
@@ -73,6 +75,7 @@ struct ConvArgs {
     float* out;            // NHWC output [N][h][w][out_cs]
     long long out_ps;
     int out_cs;
+    const float* skip;     // CONV_RES: tensor added to the output (same layout)
     int N, h, w, tiles_x, tiles_y;
     // CONV_LSTM
     const float* c_prev;   // NHWC [N][h >> cprev_up][w >> cprev_up][C] or null (zeros)
@@ -107,6 +110,9 @@ hipError_t launch_lift_last(const VecLayer& L, const float* a2, CView z, CView A
                             int N, int h, int w, int predict, float sign, int lift_int,
                             hipStream_t s);
 
+// Depth-wise 3x3 conv, NHWC float, C channels: w [9][C], b [C].
+hipError_t launch_dwconv(const float* in, const float* w, const float* b, float* out, int N, int h,
+                         int w_, int C, hipStream_t s);
 hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s);
 hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
                            float dL, float dH, int smin, int smax, int* clip, hipStream_t s);

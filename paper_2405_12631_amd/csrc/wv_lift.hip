@@ -85,6 +85,35 @@ __global__ __launch_bounds__(BLK) void lift_last_k(const VecLayer L, const float
     out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = av + sign * f;
 }
 
+// Depth-wise 3x3 conv: one thread per (position, 4 channels).
+__global__ __launch_bounds__(BLK) void dwconv_k(const float* __restrict__ in, const float* __restrict__ w,
+                                               const float* __restrict__ b, float* __restrict__ out,
+                                               int N, int h, int wd, int C) {
+    const int C4 = C / 4;
+    const long long idx = (long long)blockIdx.x * BLK + threadIdx.x;
+    const long long total = (long long)N * h * wd * C4;
+    if (idx >= total) return;
+    const int c4 = (int)(idx % C4);
+    const long long p = idx / C4;
+    const int c = (int)(p % wd);
+    const long long t = p / wd;
+    const int r = (int)(t % h);
+    const int n = (int)(t / h);
+    float4 acc = *reinterpret_cast<const float4*>(b + 4 * c4);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int rr = r + tap / 3 - 1, cc = c + tap % 3 - 1;
+        if (rr < 0 || rr >= h || cc < 0 || cc >= wd) continue;
+        const float4 v = *reinterpret_cast<const float4*>(in + (((long long)n * h + rr) * wd + cc) * C + 4 * c4);
+        const float4 k = *reinterpret_cast<const float4*>(w + tap * C + 4 * c4);
+        acc.x = fmaf(k.x, v.x, acc.x);
+        acc.y = fmaf(k.y, v.y, acc.y);
+        acc.z = fmaf(k.z, v.z, acc.z);
+        acc.w = fmaf(k.w, v.w, acc.w);
+    }
+    *reinterpret_cast<float4*>(out + p * C + 4 * c4) = acc;
+}
+
 __global__ __launch_bounds__(BLK) void center_u8_k(const uint8_t* __restrict__ x8,
                                                   float* __restrict__ xf, long long n) {
     const long long i = (long long)blockIdx.x * BLK + threadIdx.x;
@@ -279,6 +308,15 @@ hipError_t launch_lift_last(const VecLayer& L, const float* a2, CView z, CView A
                            w, predict, sign, lift_int);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_dwconv(const float* in, const float* w, const float* b, float* out, int N, int h,
+                         int w_, int C, hipStream_t s) {
+    const long long n = (long long)N * h * w_ * (C / 4);
+    if (n == 0) return hipSuccess;
+    if (C % 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(dwconv_k, dim3(nblocks(n)), dim3(BLK), 0, s, in, w, b, out, N, h, w_, C);
     return hipGetLastError();
 }
 

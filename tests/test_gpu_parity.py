@@ -294,3 +294,24 @@ def test_subband_impulse_responses_match_oracle():
     got = codec.impulse_responses(model, q_to_device(qt)[0], 64, 96).cpu().numpy()
     ref = O.subband_impulse_responses(qt, cfg, w, size=16)
     assert np.max(np.abs(got - ref)) <= XHAT_ATOL
+
+
+@pytest.mark.parametrize("name,H,W,N", [("gray64", 64, 64, 1), ("ycbcr512x768", 64, 96, 3)])
+def test_block_architecture_params_match_oracle(name, H, W, N):
+    """DepthConvBlock (step 0) and Residual Block (steps 1-3) stacks, Sec. 3.2."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("blocks", name)
+    cfg = get_config(name, ctx_arch="blocks")
+    model, w = model_for(cfg)
+    x = gradient_noise_image(H, W, seed=1)[None] if N == 1 else sinusoid_1f_planes(H, W, planes=N, seed=2)
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    ws = codec.Workspace(model, N, H, W)
+    got = codec.params_all(model, q_to_device(qs), ws)
+    ref = O.context_params_all(qs, cfg, w)
+    worst = max(param_err(got[i][g].cpu().numpy(), ref[i][g], 3) for i in range(len(ref)) for g in range(4))
+    say("blocks worst param rel err", worst)
+    assert worst <= PARAM_RTOL
+    data, q_enc = codec.encode(model, x)
+    _, _, q_dec = codec.decode(model, data)
+    assert torch.equal(q_enc, q_dec)

@@ -34,10 +34,10 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert declared == set(L.symbols())
 
 
-@pytest.mark.parametrize("name", sorted(CONFIGS))
-def test_weight_count_matches_manifest(name):
+@pytest.mark.parametrize("name,arch", [(n, a) for n in sorted(CONFIGS) for a in ("plain", "blocks")])
+def test_weight_count_matches_manifest(name, arch):
     _lib()
-    cfg = get_config(name)
+    cfg = get_config(name, ctx_arch=arch)
     n = ctypes.c_longlong()
     L.call("wv_weights_count", ctypes.byref(codec.make_config(cfg)), ctypes.byref(n))
     assert n.value * 4 == weights_nbytes(cfg)

@@ -159,3 +159,45 @@ def test_upsample_is_nearest_replication():
     np.testing.assert_array_equal(u[:, 1::2, 1::2], a)
     np.testing.assert_array_equal(u[:, 0::2, 1::2], a)
     np.testing.assert_array_equal(u[:, 1::2, 0::2], a)
+
+
+def test_block_architecture_pieces_match_torch():
+    # Depth-wise conv = torch conv2d with one group per channel; 1x1 conv = a linear map.
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal((2, 5, 6, 8))
+    w = rng.standard_normal((8, 1, 3, 3))
+    b = rng.standard_normal(8)
+    ref = torch.nn.functional.conv2d(torch.from_numpy(x).permute(0, 3, 1, 2), torch.from_numpy(w),
+                                     torch.from_numpy(b), padding=1, groups=8).permute(0, 2, 3, 1)
+    np.testing.assert_allclose(O.dwconv3x3(x, w, b), ref.numpy(), atol=1e-12)
+    w1 = rng.standard_normal((4, 8, 1, 1))
+    ref1 = torch.nn.functional.conv2d(torch.from_numpy(x).permute(0, 3, 1, 2), torch.from_numpy(w1),
+                                      torch.from_numpy(b[:4])).permute(0, 2, 3, 1)
+    np.testing.assert_allclose(O.conv1x1(x, w1, b[:4]), ref1.numpy(), atol=1e-12)
+
+
+def test_block_architecture_residual_paths_and_causality():
+    from wvgen import get_config, make_weights
+    cfg = get_config("gray64", ctx_arch="blocks")
+    w = make_weights(cfg)
+    x = np.random.default_rng(16).standard_normal((1, 6, 7, cfg["ctx_ch"]))
+    # Zero second convs leave only the skip paths: both blocks become the identity.
+    z = dict(w)
+    for k in ("p1b", "p2b"):
+        z[f"ctx.LL.0.{k}.w"] = np.zeros_like(w[f"ctx.LL.0.{k}.w"])
+        z[f"ctx.LL.0.{k}.b"] = np.zeros_like(w[f"ctx.LL.0.{k}.b"])
+    z["ctx.LL.1.rb.w"] = np.zeros_like(w["ctx.LL.1.rb.w"])
+    z["ctx.LL.1.rb.b"] = np.zeros_like(w["ctx.LL.1.rb.b"])
+    np.testing.assert_array_equal(O.depth_conv_block(x, z, "ctx.LL.0"), x)
+    np.testing.assert_array_equal(O.residual_block(x, z, "ctx.LL.1"), x)
+    assert not np.allclose(O.depth_conv_block(x, w, "ctx.LL.0"), x)
+    # Causality holds for the block stacks too.
+    xim = gradient_noise_image(64, 64, seed=1)[None]
+    qs, _ = O.quantize(O.analyze(xim, cfg, w), cfg)
+    ref = O.context_params_all(qs, cfg, w)
+    i, g = 4, 2
+    pert = [q.copy() for q in qs]
+    gm = O.group_map(*qs[i].shape[1:])
+    pert[i] = np.where(gm[None] >= g, np.clip(qs[i] + 9, -64, 64), qs[i])
+    got = O.step_params(pert[i], O.long_context(pert, cfg, w, upto=i + 1)[i], 1, g, cfg, w)
+    assert np.array_equal(got, ref[i][g])

@@ -10,6 +10,7 @@ _BASE = dict(
     lift_layers=3,      # conv3x3 layers inside one predict/update filter
     mix_k=3,            # mixture components per coefficient
     dist="gauss",       # component family: "gauss" or "laplace"
+    ctx_arch="plain",   # step stacks: "plain" conv stacks or "blocks" (DepthConv / Residual)
     sym_min=-64,        # symbol alphabet [sym_min, sym_max]
     sym_max=64,
     cdf_bits=16,        # CDF tables are 16-bit integers summing to 2**cdf_bits

@@ -14,6 +14,10 @@ Manifest order:
      g in 0..3 inner, each `ctx_layers` convs: Cin_g -> ctx_ch,
      (ctx_ch -> ctx_ch) x (ctx_layers - 2), ctx_ch -> 3*mix_k, where Cin_0 =
      ctx_ch and Cin_g = 1 + ctx_ch for g >= 1 with channel 0 the symbol channel.
+     With ctx_arch == "blocks" a stack is instead: in (3x3, Cin_g -> C), then
+     for g = 0 a DepthConvBlock p1a (1x1), dw (depth-wise 3x3, weight
+     [C][1][3][3]), p1b (1x1), p2a (1x1), p2b (1x1), for g >= 1 a Residual
+     Block ra, rb (3x3), then out (3x3, C -> 3K).
 """
 import numpy as np
 
@@ -36,8 +40,8 @@ def manifest(cfg):
     """List of (name, shape) in blob order."""
     out = []
 
-    def conv(prefix, cin, cout):
-        out.append((prefix + ".w", (cout, cin, 3, 3)))
+    def conv(prefix, cin, cout, k=3):
+        out.append((prefix + ".w", (cout, cin, k, k)))
         out.append((prefix + ".b", (cout,)))
 
     for nm in LIFT_NAMES:
@@ -46,11 +50,27 @@ def manifest(cfg):
             conv(f"lift.{nm}.{l}", ch[l], ch[l + 1])
     C = cfg["ctx_ch"]
     conv("lstm", 1 + C, 4 * C)
+    blocks = cfg.get("ctx_arch", "plain") == "blocks"
     for t in TYPE_NAMES:
         for g in range(4):
-            ch = _ctx_chain(cfg, g)
-            for l in range(len(ch) - 1):
-                conv(f"ctx.{t}.{g}.{l}", ch[l], ch[l + 1])
+            if not blocks:
+                ch = _ctx_chain(cfg, g)
+                for l in range(len(ch) - 1):
+                    conv(f"ctx.{t}.{g}.{l}", ch[l], ch[l + 1])
+                continue
+            pre = f"ctx.{t}.{g}"
+            conv(pre + ".in", C if g == 0 else C + 1, C)
+            if g == 0:   # DepthConvBlock: 1x1, depth-wise 3x3, 1x1 | 1x1, 1x1
+                conv(pre + ".p1a", C, C, 1)
+                out.append((pre + ".dw.w", (C, 1, 3, 3)))
+                out.append((pre + ".dw.b", (C,)))
+                conv(pre + ".p1b", C, C, 1)
+                conv(pre + ".p2a", C, C, 1)
+                conv(pre + ".p2b", C, C, 1)
+            else:        # Residual Block: 3x3, 3x3
+                conv(pre + ".ra", C, C)
+                conv(pre + ".rb", C, C)
+            conv(pre + ".out", C, 3 * cfg["mix_k"])
     return out
 
 
@@ -61,7 +81,7 @@ def make_weights(cfg):
     pending_bound = None
     for name, shape in manifest(cfg):
         if name.endswith(".w"):
-            pending_bound = 1.0 / np.sqrt(9.0 * shape[1])
+            pending_bound = 1.0 / np.sqrt(float(shape[1] * shape[2] * shape[3]))
         out[name] = rng.uniform(-pending_bound, pending_bound, shape).astype(np.float32)
     return out
 
