@@ -72,6 +72,9 @@ typedef struct wv_config {
     int dist;        /* wv_dist: mixture component family                     */
     int ctx_arch;    /* 0: plain conv stacks; 1: DepthConvBlock (step 0) and
                         Residual Block (steps 1-3) stacks, Sec. 3.2 (FP32 only) */
+    int ll_ar;       /* 1: LL_J coded autoregressively in raster order (Sec. 3.2,
+                        the paper's default) instead of in four steps      */
+    int ar_ch;       /* channels of the autoregressive LL model (32 or 64)    */
 } wv_config;
 
 /* One subband of the packed layout. type: 0 LL, 1 HL, 2 LH, 3 HH. */
@@ -100,6 +103,9 @@ int wv_version(void);
  *       DepthConvBlock p1a (1x1 [C][C][1][1]), dw (depth-wise [C][1][3][3]),
  *       p1b, p2a, p2b (1x1); steps 1-3 a Residual Block ra, rb (3x3 C -> C);
  *       out (3x3, C -> 3K).
+ *   With ll_ar = 1, appended: ar.0 (5x5, 1 -> ar_ch; only the 12 causal taps,
+ *       the two rows above and the two positions to the left, are used),
+ *       ar.1 (1x1, ar_ch -> ar_ch), ar.2 (1x1, ar_ch -> 3K).
  * wv_weights_count: number of floats of that blob for cfg.
  */
 int wv_weights_count(const wv_config* cfg, long long* n_floats);
@@ -189,6 +195,29 @@ int wv_context_params(const wv_model* m, const int16_t* d_q, int nplanes, int H,
  */
 int wv_cdf_tables(const float* d_params, long long n, int mix_k, int dist, int sym_min,
                   int sym_max, int cdf_bits, uint16_t* d_cdf, void* stream);
+
+/*
+ * Autoregressive LL model (ll_ar = 1; Sec. 3.2, Fig. 4a: the LL subband is
+ * coded from its own causal spatial context, one symbol at a time in raster
+ * order).  Parameters of a position: its 12 causal neighbours in a 5x5 window
+ * (zero outside the subband) -> ReLU(conv) -> ReLU(1x1) -> 1x1 -> the mixture
+ * head of wv_context_params.
+ *   wv_ar_params: encoder side; every LL position of every plane at once from
+ *     the known symbols d_q; d_params float [nplanes][h_J * w_J][3K] in raster
+ *     order (rows for wv_cdf_tables; the plane's stream is one rANS stream
+ *     over the raster order).
+ *   wv_ar_decode: decoder side; walks LL in raster order on the GPU, one
+ *     workgroup per plane, computing each position's parameters and CDF row
+ *     and rANS-decoding its symbol in the kernel (stream format of
+ *     wv_rans_decode).  d_bytes: the planes' LL streams back to back,
+ *     d_offsets int64 [nplanes + 1] (device); writes LL of d_q; d_status int
+ *     [nplanes]: 0, or 1 for a corrupt or truncated stream (the walk still
+ *     finishes).  Needs w_J <= 4096.
+ */
+int wv_ar_params(const wv_model* m, const int16_t* d_q, int nplanes, int H, int W,
+                 float* d_params, void* stream);
+int wv_ar_decode(const wv_model* m, const uint8_t* d_bytes, const long long* d_offsets,
+                 int nplanes, int H, int W, int16_t* d_q, int* d_status, void* stream);
 
 /* Write decoded symbol indices (symbol - sym_min) of step `step` of subband
  * `subband` into the packed symbols: d_sym uint8 [nplanes][n_g]. */

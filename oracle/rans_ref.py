@@ -70,3 +70,33 @@ def rans_decode_ref(cdf, data, n):
             pos += 1
         out[k] = s
     return out
+
+
+class RansDecoderRef:
+    """Symbol-at-a-time decoder for streams whose next CDF row depends on the
+    symbols decoded so far (the autoregressive LL model)."""
+
+    def __init__(self, data):
+        self.data = bytes(data)
+        if len(self.data) < 4:
+            raise ValueError("truncated stream")
+        self.x = int.from_bytes(self.data[:4], "little")
+        self.pos = 4
+
+    def next(self, cdf_row):
+        r = _row(cdf_row)
+        slot = self.x & (_M - 1)
+        s = 0
+        while r[s + 1] <= slot:
+            s += 1
+        self.x = (r[s + 1] - r[s]) * (self.x >> _PROB_BITS) + slot - r[s]
+        while self.x < _L:
+            if self.pos >= len(self.data):
+                raise ValueError("truncated stream")
+            self.x = (self.x << 8) | self.data[self.pos]
+            self.pos += 1
+        return s
+
+    def finish(self):
+        if self.x != _L or self.pos != len(self.data):
+            raise ValueError("stream not fully consumed")

@@ -422,6 +422,30 @@ def step_params(q_i, l_i, t, g, cfg, weights):
     return mixture_head(r[:, rr, cc, :], cfg)
 
 
+# Causal 5x5 neighbourhood of the autoregressive LL model (raster order): the two
+# rows above and the two positions to the left.
+AR_TAPS = tuple((dy, dx) for dy in (-2, -1) for dx in (-2, -1, 0, 1, 2)) + ((0, -2), (0, -1))
+
+
+def ar_params(q_ll, cfg, weights):
+    """Autoregressive context model of the LL subband (Sec. 3.2, Fig. 4a: LL is coded
+    from its own causal spatial context only).  Reading: a 5x5 masked conv over the 12
+    already-coded neighbours (zero outside the subband), ReLU, 1x1 conv, ReLU, 1x1 conv
+    to 3K, the same mixture head.  q_ll [N][h][w] -> params [N][h*w][3K], raster order."""
+    q = np.asarray(q_ll, np.float64)
+    N, h, w = q.shape
+    qp = np.pad(q, ((0, 0), (2, 2), (2, 2)))
+    W0, b0 = _wb(weights, "ar.0")
+    a = np.empty((N, h, w, W0.shape[0]))
+    a[...] = b0
+    for dy, dx in AR_TAPS:
+        a += qp[:, 2 + dy:2 + dy + h, 2 + dx:2 + dx + w, None] * W0[:, 0, dy + 2, dx + 2]
+    a = np.maximum(a, 0.0)
+    a = np.maximum(conv1x1(a, *_wb(weights, "ar.1")), 0.0)
+    r = conv1x1(a, *_wb(weights, "ar.2"))
+    return mixture_head(r.reshape(N, h * w, -1), cfg)
+
+
 def context_params_all(qs, cfg, weights):
     """Parameters of every (subband, step) in coding order, from the complete q.
 
@@ -431,8 +455,11 @@ def context_params_all(qs, cfg, weights):
     """
     ls = long_context(qs, cfg, weights)
     lay = [s["type"] for s in subband_layout(cfg, *_image_hw(qs, cfg))[0]]
-    return [[step_params(qs[i], ls[i], lay[i], g, cfg, weights) for g in range(4)]
-            for i in range(len(qs))]
+    out = [[step_params(qs[i], ls[i], lay[i], g, cfg, weights) for g in range(4)]
+           for i in range(len(qs))]
+    if cfg.get("ll_ar", 0):
+        out[0] = [ar_params(qs[0], cfg, weights)]   # one raster-order step
+    return out
 
 
 def _image_hw(qs, cfg):
@@ -524,6 +551,11 @@ def encode(x, cfg, weights):
     N = qs[0].shape[0]
     streams = [[[None] * 4 for _ in qs] for _ in range(N)]
     for i, q in enumerate(qs):
+        if i == 0 and cfg.get("ll_ar", 0):
+            for n in range(N):
+                streams[n][0] = [rans_encode_ref(cdf_tables(prm[0][0][n], cfg),
+                                                 q[n].ravel() - cfg["sym_min"]), b"", b"", b""]
+            continue
         for g in range(4):
             rr, cc = group_positions(q.shape[1], q.shape[2], g)
             for n in range(N):
@@ -549,6 +581,17 @@ def decode_symbols(streams, cfg, weights, H, W, N):
         if u.shape[1] != s["h"]:
             u = upsample2(u)
         hs, cs = lstm_cell(conv3x3(np.concatenate([u[..., None], hs], -1), wl, bl), cs)
+        if i == 0 and cfg.get("ll_ar", 0):
+            # Raster order, one symbol at a time, from the symbols decoded so far.
+            from .rans_ref import RansDecoderRef
+            for n in range(N):
+                dec = RansDecoderRef(streams[n][0][0])
+                for p in range(s["h"] * s["w"]):
+                    r, c = divmod(p, s["w"])
+                    prm = ar_params(qs[0][n:n + 1], cfg, weights)[0, p]
+                    qs[0][n, r, c] = dec.next(cdf_tables(prm[None], cfg)[0]) + cfg["sym_min"]
+                dec.finish()
+            continue
         for g in range(4):
             prm = step_params(qs[i], hs, s["type"], g, cfg, weights)
             rr, cc = group_positions(s["h"], s["w"], g)

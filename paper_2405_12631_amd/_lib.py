@@ -32,7 +32,7 @@ class wv_config(ctypes.Structure):
                 ("ctx_ch", ctypes.c_int), ("ctx_layers", ctypes.c_int), ("mix_k", ctypes.c_int),
                 ("sym_min", ctypes.c_int), ("sym_max", ctypes.c_int), ("cdf_bits", ctypes.c_int),
                 ("sigma_min", ctypes.c_float), ("lift_int", ctypes.c_int), ("dist", ctypes.c_int),
-                ("ctx_arch", ctypes.c_int)]
+                ("ctx_arch", ctypes.c_int), ("ll_ar", ctypes.c_int), ("ar_ch", ctypes.c_int)]
 
 
 class wv_subband(ctypes.Structure):
@@ -60,6 +60,8 @@ _SIGS = {
     "wv_analyze": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P, _P]),
     "wv_context_params": (_I, [_P, _P, _I, _I, _I, _I, _I, _P, _P, _P, _P]),
     "wv_cdf_tables": (_I, [_P, _LL, _I, _I, _I, _I, _I, _P, _P]),
+    "wv_ar_params": (_I, [_P, _P, _I, _I, _I, _P, _P]),
+    "wv_ar_decode": (_I, [_P, _P, _P, _I, _I, _I, _P, _P, _P]),
     "wv_scatter_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_gather_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_synthesize": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P]),

@@ -26,7 +26,8 @@ def make_config(cfg):
                        sym_min=cfg["sym_min"], sym_max=cfg["sym_max"], cdf_bits=cfg["cdf_bits"],
                        sigma_min=cfg["sigma_min"], lift_int=int(cfg.get("lift_int", 0)),
                        dist=L.DISTS[cfg.get("dist", "gauss")],
-                       ctx_arch=1 if cfg.get("ctx_arch", "plain") == "blocks" else 0)
+                       ctx_arch=1 if cfg.get("ctx_arch", "plain") == "blocks" else 0,
+                       ll_ar=int(cfg.get("ll_ar", 0)), ar_ch=int(cfg.get("ar_ch", 32)))
 
 
 def _ptr(t):
@@ -194,13 +195,41 @@ def temporal_haar(frames, inverse=False):
     return frames
 
 
+def ar_params(model, q, ws, out=None):
+    """Autoregressive LL model, encoder side: [N, h_J * w_J, 3K] in raster order."""
+    s = ws.lay[0]
+    n0 = s["h"] * s["w"]
+    K = model.cfg["mix_k"]
+    if out is None:
+        out = ws.params[:ws.N * n0 * 3 * K]
+    L.call("wv_ar_params", model.h, _ptr(q), ws.N, ws.H, ws.W, _ptr(out), _stream())
+    return out.view(ws.N, n0, 3 * K)
+
+
+def ar_decode(model, q, ws, ll_streams):
+    """Decode LL of every plane on the GPU from its raster-order streams (list of bytes)."""
+    offs = np.zeros(ws.N + 1, np.int64)
+    offs[1:] = np.cumsum([len(b) for b in ll_streams])
+    blob = np.frombuffer(b"".join(ll_streams) + b"\0", np.uint8)
+    d_bytes = torch.from_numpy(blob.copy()).to(q.device)
+    d_offs = torch.from_numpy(offs).to(q.device)
+    status = torch.zeros(ws.N, dtype=torch.int32, device=q.device)
+    L.call("wv_ar_decode", model.h, _ptr(d_bytes), _ptr(d_offs), ws.N, ws.H, ws.W, _ptr(q),
+           _ptr(status), _stream())
+    if int(status.sum().item()):
+        raise L.WvError(L.WV_ECORRUPT, "corrupt LL stream")
+
+
 def params_all(model, q, ws):
-    """Teacher-forced parameters of every (subband, step): list [i][g] of [N, n_g, 3K] copies."""
+    """Teacher-forced parameters of every (subband, step): list [i][g] of [N, n_g, 3K] copies.
+    With the autoregressive LL model, subband 0 has one raster-order entry."""
     out = []
     for i in range(len(ws.lay)):
         row = []
         for g in range(4):
             row.append(context_params(model, q, ws, i, g).clone())
+        if i == 0 and model.cfg.get("ll_ar", 0):
+            row = [ar_params(model, q, ws).clone()]
         out.append(row)
     return out
 
@@ -288,6 +317,16 @@ def encode(model, planes, ws=None):
     q, _, _ = analyze(model, x, ws)
     streams = [[[None] * 4 for _ in ws.lay] for _ in range(N)]
     for i, s in enumerate(ws.lay):
+        if i == 0 and model.cfg.get("ll_ar", 0):
+            context_params(model, q, ws, 0, 0)          # advances the long context only
+            cdf = cdf_tables(model, ar_params(model, q, ws), out=ws.cdf)
+            n0 = s["h"] * s["w"]
+            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            sym_h = (q[:, :n0].cpu().numpy().astype(np.int32) - model.cfg["sym_min"]).astype(np.uint8)
+            for n in range(N):
+                streams[n][0] = [rans_encode(cdf_h[n * n0:(n + 1) * n0], sym_h[n], model.nsym),
+                                 b"", b"", b""]
+            continue
         for g in range(4):
             prm = context_params(model, q, ws, i, g)
             cdf = cdf_tables(model, prm, out=ws.cdf)
@@ -308,6 +347,10 @@ def decode(model, data, ws=None, want_u8=True):
     ws = ws or Workspace(model, N, H, W)
     q = torch.zeros((N, H * W), dtype=torch.int16, device=model.device)
     for i, s in enumerate(ws.lay):
+        if i == 0 and model.cfg.get("ll_ar", 0):
+            context_params(model, q, ws, 0, 0)          # advances the long context only
+            ar_decode(model, q, ws, [streams[n][0][0] for n in range(N)])
+            continue
         for g in range(4):
             prm = context_params(model, q, ws, i, g)
             cdf = cdf_tables(model, prm, out=ws.cdf)

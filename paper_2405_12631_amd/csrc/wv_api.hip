@@ -56,6 +56,8 @@ static int check_cfg(const wv_config* c) {
     if (!(c->sigma_min > 0.f)) return fail(WV_EINVAL, "sigma_min must be > 0");
     if (c->dist != WV_DIST_GAUSS && c->dist != WV_DIST_LAPLACE) return fail(WV_EINVAL, "bad dist");
     if (c->ctx_arch != 0 && c->ctx_arch != 1) return fail(WV_EINVAL, "bad ctx_arch");
+    if (c->ll_ar != 0 && c->ll_ar != 1) return fail(WV_EINVAL, "bad ll_ar");
+    if (c->ll_ar && c->ar_ch != 32 && c->ar_ch != 64) return fail(WV_EUNSUPPORTED, "ar_ch must be 32 or 64");
     return WV_OK;
 }
 
@@ -77,6 +79,7 @@ struct Manifest {
     ConvShape lstm;
     std::vector<ConvShape> ctx[4][4]; // [type][step], plain stacks
     BlockShapes blk[4][4];            // [type][step], ctx_arch == 1
+    ConvShape ar0, ar1, ar2;          // ll_ar == 1: 5x5 (1 -> A), 1x1 (A -> A), 1x1 (A -> 3K)
     long long total = 0;
 };
 
@@ -123,6 +126,11 @@ Manifest make_manifest(const wv_config& c) {
             ch.push_back(3 * c.mix_k);
             for (size_t l = 0; l + 1 < ch.size(); ++l) m.ctx[t][g].push_back(conv(ch[l], ch[l + 1]));
         }
+    if (c.ll_ar) {
+        m.ar0 = conv(1, c.ar_ch, 25);
+        m.ar1 = conv(c.ar_ch, c.ar_ch, 1);
+        m.ar2 = conv(c.ar_ch, 3 * c.mix_k, 1);
+    }
     m.total = off;
     return m;
 }
@@ -292,7 +300,12 @@ struct HostModel {
     MfmaRef lstm;
     std::vector<MfmaRef> ctx[4][4];
     BlockRefs blk[4][4];
+    size_t ar_w1, ar_b1, ar_w2, ar_b2, ar_w3, ar_b3;
 };
+
+// Raster-order offsets (dy, dx) of the 12 causal taps of the AR model's 5x5 window.
+static const int kArDy[12] = {-2, -2, -2, -2, -2, -1, -1, -1, -1, -1, 0, 0};
+static const int kArDx[12] = {-2, -1, 0, 1, 2, -2, -1, 0, 1, 2, -2, -1};
 
 // Context layers are packed for the precision's kernel; lifting is always FP32.
 HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c, int precision) {
@@ -336,6 +349,27 @@ HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c, int preci
             for (size_t l = 0; l < v.size(); ++l)
                 hm.ctx[t][g].push_back(ctxpack(pb, blob, v[l], (l == 0 && g > 0) ? 1 : 0, false, 0));
         }
+    if (c.ll_ar) {
+        const int A = c.ar_ch, O3 = 3 * c.mix_k;
+        hm.ar_w1 = pb.add((size_t)A * 12);
+        hm.ar_b1 = pb.add(A);
+        hm.ar_w2 = pb.add((size_t)A * A);
+        hm.ar_b2 = pb.add(A);
+        hm.ar_w3 = pb.add((size_t)O3 * A);
+        hm.ar_b3 = pb.add(O3);
+        for (int k = 0; k < A; ++k) {
+            for (int t = 0; t < 12; ++t)
+                pb.data[hm.ar_w1 + k * 12 + t] =
+                    blob[mf.ar0.w_off + (long long)k * 25 + (kArDy[t] + 2) * 5 + (kArDx[t] + 2)];
+            pb.data[hm.ar_b1 + k] = blob[mf.ar0.b_off + k];
+            for (int j = 0; j < A; ++j) pb.data[hm.ar_w2 + k * A + j] = blob[mf.ar1.w_off + (long long)k * A + j];
+            pb.data[hm.ar_b2 + k] = blob[mf.ar1.b_off + k];
+        }
+        for (int o = 0; o < O3; ++o) {
+            for (int j = 0; j < A; ++j) pb.data[hm.ar_w3 + o * A + j] = blob[mf.ar2.w_off + (long long)o * A + j];
+            pb.data[hm.ar_b3 + o] = blob[mf.ar2.b_off + o];
+        }
+    }
     return hm;
 }
 
@@ -355,6 +389,7 @@ struct wv_model {
         const float* dw_w;
         const float* dw_b;
     } blk[4][4];
+    ArModel ar;                          // ll_ar == 1
 };
 
 static int check_precision(const wv_config* c, int precision) {
@@ -464,6 +499,10 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
                 }
             }
     }
+    if (cfg->ll_ar)
+        m->ar = ArModel{base + hm.ar_w1, base + hm.ar_b1, base + hm.ar_w2, base + hm.ar_b2,
+                        base + hm.ar_w3, base + hm.ar_b3, cfg->ar_ch, cfg->mix_k, cfg->dist,
+                        cfg->sigma_min};
     *out = m;
     return WV_OK;
 }
@@ -958,6 +997,36 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
         }
         if (!last) in = act[l & 1];
     }
+    return WV_OK;
+}
+
+extern "C" int wv_ar_params(const wv_model* m, const int16_t* d_q, int N, int H, int W,
+                            float* d_params, void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (!m->cfg.ll_ar) return fail(WV_EUNSUPPORTED, "model has no autoregressive LL model");
+    if (!d_q || !d_params) return fail(WV_EINVAL, "null pointer");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    HIPCHK(launch_ar_params(m->ar, d_q + lay[0].off, (long long)H * W, lay[0].h, lay[0].w, N, d_params,
+                            (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" int wv_ar_decode(const wv_model* m, const uint8_t* d_bytes, const long long* d_offsets,
+                            int N, int H, int W, int16_t* d_q, int* d_status, void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (!m->cfg.ll_ar) return fail(WV_EUNSUPPORTED, "model has no autoregressive LL model");
+    if (!d_bytes || !d_offsets || !d_q || !d_status) return fail(WV_EINVAL, "null pointer");
+    if (N < 1) return fail(WV_ESHAPE, "nplanes must be >= 1");
+    std::vector<Sub> lay;
+    int rc = layout(m->cfg, H, W, lay);
+    if (rc) return rc;
+    if (lay[0].w > 4096) return fail(WV_ESHAPE, "LL subband wider than 4096");
+    const int nsym = m->cfg.sym_max - m->cfg.sym_min + 1;
+    HIPCHK(launch_ar_decode(m->ar, ArStreams{d_bytes, d_offsets}, d_q + lay[0].off, (long long)H * W,
+                            lay[0].h, lay[0].w, N, m->cfg.sym_min, nsym, d_status, (hipStream_t)stream));
     return WV_OK;
 }
 

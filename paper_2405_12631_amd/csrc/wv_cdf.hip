@@ -14,6 +14,7 @@
 //   * a running maximum makes the row non-decreasing.
 // One thread builds one row in LDS; the 64 rows of a workgroup are then
 // written out as one contiguous, coalesced block.
+#include "wv_device.h"
 #include "wv_internal.h"
 
 namespace wv {
@@ -21,14 +22,6 @@ namespace {
 
 constexpr int ROWS = 64;
 constexpr int MAXE = 256;   // max entries per row (N_s + 1)
-
-// Smaller tail of a standard component at |z|: Gaussian 0.5 erfc(|z|/sqrt 2),
-// Laplace 0.5 exp(-|z|).  TAILZ: |z| beyond which the tail is < 1/(2^16 F_max)
-// scale, i.e. 0 < tail * F_max < 1 (Gaussian 6: 1e-9; Laplace 12: 3e-6).
-template <int DIST>
-__device__ __forceinline__ float tail_of(float az) {
-    return DIST == WV_DIST_GAUSS ? 0.5f * erfcf(az * 0.70710678118654752f) : 0.5f * expf(-az);
-}
 
 template <int K, int DIST>
 __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, long long n, int smin,
@@ -41,58 +34,12 @@ __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, 
     const int nrows = (int)((n - row0) < ROWS ? (n - row0) : ROWS);
     uint16_t* my = rows + t * E;
     if (row < n) {
-        const float* p = params + row * (3 * K);
-        float w[K], mu[K], sg[K];
-        float S = 0.f, lo = 3.0e38f, hi = -3.0e38f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            w[k] = p[k];
-            mu[k] = p[K + k];
-            sg[k] = p[2 * K + k];
-            S += w[k];
-            constexpr float TZ = DIST == WV_DIST_GAUSS ? 6.0f : 12.0f;
-            lo = fminf(lo, mu[k] - TZ * sg[k]);
-            hi = fmaxf(hi, mu[k] + TZ * sg[k]);
-        }
-        const float invS = 1.0f / S;
-        const int Fmax = 65536 - nsym;
-        // Boundary b_j = smin + j - 0.5.  j < jlo: b_j <= lo; j > jhi: b_j >= hi.
-        const float flo = fminf(fmaxf(floorf(lo - (float)smin + 0.5f) + 1.0f, 1.0f), (float)nsym);
-        const float fhi = fminf(fmaxf(ceilf(hi - (float)smin + 0.5f) - 1.0f, 0.0f), (float)(nsym - 1));
-        const int jlo = (int)flo;
-        const int jhi = (int)fhi;
+        CdfRow<K, DIST> R;
+        cdf_setup<K, DIST>(params + row * (3 * K), smin, nsym, R);
         my[0] = 0;
         int F = 0;
         for (int j = 1; j < nsym; ++j) {
-            int Fj;
-            if (j < jlo) {
-                Fj = 0;
-            } else if (j > jhi) {
-                Fj = Fmax - 1;
-            } else {
-                const float b = (float)(smin + j) - 0.5f;
-                float L = 0.f, U = 0.f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const float z = (b - mu[k]) / sg[k];
-                    const float tail = tail_of<DIST>(fabsf(z));
-                    if (z < 0.f) {
-                        L = fmaf(w[k], tail, L);
-                        U = fmaf(w[k], 1.0f - tail, U);
-                    } else {
-                        L = fmaf(w[k], 1.0f - tail, L);
-                        U = fmaf(w[k], tail, U);
-                    }
-                }
-                L *= invS;
-                U *= invS;
-                if (L <= U) {
-                    Fj = (int)floorf((float)Fmax * L);
-                } else {
-                    const int up = (int)ceilf((float)Fmax * U);
-                    Fj = Fmax - (up < 1 ? 1 : up);
-                }
-            }
+            const int Fj = cdf_F<K, DIST>(R, j);
             F = Fj > F ? Fj : F;
             my[j] = (uint16_t)(j + F);
         }

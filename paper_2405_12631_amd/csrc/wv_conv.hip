@@ -17,6 +17,7 @@
 // symbol channel (int16 symbols, masked by coding step) is a separate
 // rank-9 update of three K=4 chunks.  Accumulation order is fixed, so a
 // position's result does not depend on the tile, the grid or the batch.
+#include "wv_device.h"
 #include "wv_internal.h"
 
 namespace wv {
@@ -297,21 +298,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                 const int hg = (a.h - gr + 1) >> 1;
                 const long long gi = (long long)(r >> 1) * wg + (c >> 1);
                 float* o = a.params + ((long long)n * hg * wg + gi) * 3 * K;
-                float mx = v[0];
-                for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
-                float e[4];
-                float se = 0.f;
-                for (int k = 0; k < K; ++k) {
-                    e[k] = __expf(v[k] - mx);
-                    se += e[k];
-                }
-                for (int k = 0; k < K; ++k) o[k] = e[k] / se;
-                for (int k = 0; k < K; ++k) o[K + k] = v[K + k];
-                for (int k = 0; k < K; ++k) {
-                    const float x = v[2 * K + k];
-                    const float sp = log1pf(__expf(-fabsf(x))) + fmaxf(x, 0.f);
-                    o[2 * K + k] = fmaxf(sp, a.sigma_min);
-                }
+                mixture_head(v, K, a.sigma_min, o);
             }
         }
     }

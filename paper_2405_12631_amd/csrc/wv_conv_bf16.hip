@@ -10,6 +10,7 @@
 // B fragments: per-tap weight slices staged in LDS, double buffered, fetched
 // into registers one tap ahead.  Activations in and out are BF16 (NHWC), the
 // LSTM cell state, every epilogue and the mixture parameters are FP32.
+#include "wv_device.h"
 #include "wv_internal.h"
 
 namespace wv {
@@ -267,21 +268,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, co
                 const int hg = (a.h - gr + 1) >> 1;
                 const long long gi = (long long)(r >> 1) * wg2 + (c >> 1);
                 float* o = a.params + ((long long)n * hg * wg2 + gi) * 3 * K;
-                float mx = v[0];
-                for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
-                float e[4];
-                float se = 0.f;
-                for (int k = 0; k < K; ++k) {
-                    e[k] = __expf(v[k] - mx);
-                    se += e[k];
-                }
-                for (int k = 0; k < K; ++k) o[k] = e[k] / se;
-                for (int k = 0; k < K; ++k) o[K + k] = v[K + k];
-                for (int k = 0; k < K; ++k) {
-                    const float x = v[2 * K + k];
-                    const float sp = log1pf(__expf(-fabsf(x))) + fmaxf(x, 0.f);
-                    o[2 * K + k] = fmaxf(sp, a.sigma_min);
-                }
+                mixture_head(v, K, a.sigma_min, o);
             }
         }
     }

@@ -1,0 +1,99 @@
+// Device functions shared by several kernels.  Each computes its values with
+// one fixed sequence of FP32 operations, so the encoder's and the decoder's
+// kernels produce identical bits from identical inputs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wv.h"
+
+namespace wv {
+
+// Mixture head (Sec. 3.1 / 3.2 entropy parameters): raw 3K values ->
+// w = softmax(v[0:K]), mu = v[K:2K], sigma = max(softplus(v[2K:3K]), sigma_min).
+__device__ __forceinline__ void mixture_head(const float* v, int K, float sigma_min, float* o) {
+    float mx = v[0];
+    for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
+    float e[4];
+    float se = 0.f;
+    for (int k = 0; k < K; ++k) {
+        e[k] = __expf(v[k] - mx);
+        se += e[k];
+    }
+    for (int k = 0; k < K; ++k) o[k] = e[k] / se;
+    for (int k = 0; k < K; ++k) o[K + k] = v[K + k];
+    for (int k = 0; k < K; ++k) {
+        const float x = v[2 * K + k];
+        const float sp = log1pf(__expf(-fabsf(x))) + fmaxf(x, 0.f);
+        o[2 * K + k] = fmaxf(sp, sigma_min);
+    }
+}
+
+// One row of the 16-bit CDF table (see wv_cdf_tables): setup from the
+// parameters, then F_j before the running maximum.
+template <int K, int DIST>
+struct CdfRow {
+    float w[K], mu[K], sg[K];
+    float invS;
+    int jlo, jhi, Fmax, smin;
+};
+
+// Smaller tail of a standard component at |z|: Gaussian 0.5 erfc(|z|/sqrt 2),
+// Laplace 0.5 exp(-|z|).
+template <int DIST>
+__device__ __forceinline__ float tail_of(float az) {
+    return DIST == WV_DIST_GAUSS ? 0.5f * erfcf(az * 0.70710678118654752f) : 0.5f * expf(-az);
+}
+
+template <int K, int DIST>
+__device__ __forceinline__ void cdf_setup(const float* p, int smin, int nsym, CdfRow<K, DIST>& R) {
+    // Beyond TZ scales every component's tail is below 1/F_max: Gaussian 6
+    // (Phi(-6) = 1e-9), Laplace 12 (exp(-12)/2 = 3e-6).
+    constexpr float TZ = DIST == WV_DIST_GAUSS ? 6.0f : 12.0f;
+    float S = 0.f, lo = 3.0e38f, hi = -3.0e38f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        R.w[k] = p[k];
+        R.mu[k] = p[K + k];
+        R.sg[k] = p[2 * K + k];
+        S += R.w[k];
+        lo = fminf(lo, R.mu[k] - TZ * R.sg[k]);
+        hi = fmaxf(hi, R.mu[k] + TZ * R.sg[k]);
+    }
+    R.invS = 1.0f / S;
+    R.Fmax = 65536 - nsym;
+    R.smin = smin;
+    // Boundary b_j = smin + j - 0.5.  j < jlo: b_j <= lo; j > jhi: b_j >= hi.
+    R.jlo = (int)fminf(fmaxf(floorf(lo - (float)smin + 0.5f) + 1.0f, 1.0f), (float)nsym);
+    R.jhi = (int)fminf(fmaxf(ceilf(hi - (float)smin + 0.5f) - 1.0f, 0.0f), (float)(nsym - 1));
+}
+
+// F_j = floor(F_max C_j) as in exact arithmetic (lower tail where C_j <= 1/2, else
+// F_max - ceil(F_max (1 - C_j)) with at least one count below F_max).
+template <int K, int DIST>
+__device__ __forceinline__ int cdf_F(const CdfRow<K, DIST>& R, int j) {
+    if (j < R.jlo) return 0;
+    if (j > R.jhi) return R.Fmax - 1;
+    const float b = (float)(R.smin + j) - 0.5f;
+    float L = 0.f, U = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float z = (b - R.mu[k]) / R.sg[k];
+        const float tail = tail_of<DIST>(fabsf(z));
+        if (z < 0.f) {
+            L = fmaf(R.w[k], tail, L);
+            U = fmaf(R.w[k], 1.0f - tail, U);
+        } else {
+            L = fmaf(R.w[k], 1.0f - tail, L);
+            U = fmaf(R.w[k], tail, U);
+        }
+    }
+    L *= R.invS;
+    U *= R.invS;
+    if (L <= U) return (int)floorf((float)R.Fmax * L);
+    const int up = (int)ceilf((float)R.Fmax * U);
+    return R.Fmax - (up < 1 ? 1 : up);
+}
+
+}  // namespace wv

@@ -113,6 +113,23 @@ hipError_t launch_lift_last(const VecLayer& L, const float* a2, CView z, CView A
 // Depth-wise 3x3 conv, NHWC float, C channels: w [9][C], b [C].
 hipError_t launch_dwconv(const float* in, const float* w, const float* b, float* out, int N, int h,
                          int w_, int C, hipStream_t s);
+// Autoregressive LL model (wv_ar.hip): 12 causal taps of a 5x5 window.
+constexpr int AR_TAPS = 12;
+struct ArModel {
+    const float *w1, *b1;   // [A][12] (taps in raster order of the window), [A]
+    const float *w2, *b2;   // [A][A], [A]
+    const float *w3, *b3;   // [3K][A], [3K]
+    int A, K, dist;
+    float sigma_min;
+};
+struct ArStreams {
+    const uint8_t* bytes;    // all planes' LL streams back to back
+    const long long* offs;   // device [N + 1]: plane n's stream is bytes[offs[n] .. offs[n+1])
+};
+hipError_t launch_ar_params(const ArModel& M, const int16_t* q, long long q_ps, int h, int w, int N,
+                            float* params, hipStream_t s);
+hipError_t launch_ar_decode(const ArModel& M, const ArStreams& S, int16_t* q, long long q_ps, int h,
+                            int w, int N, int smin, int nsym, int* status, hipStream_t s);
 hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s);
 hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
                            float dL, float dH, int smin, int smax, int* clip, hipStream_t s);

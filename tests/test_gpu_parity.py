@@ -315,3 +315,32 @@ def test_block_architecture_params_match_oracle(name, H, W, N):
     data, q_enc = codec.encode(model, x)
     _, _, q_dec = codec.decode(model, data)
     assert torch.equal(q_enc, q_dec)
+
+
+@pytest.mark.parametrize("name,H,W,N", [("gray64", 64, 64, 1), ("ycbcr512x768", 64, 96, 3)])
+def test_autoregressive_ll_model(name, H, W, N):
+    """The paper's default LL coding (Sec. 3.2): raster order, decoded on the GPU."""
+    need_gpu()
+    from paper_2405_12631_amd import codec, _lib as L
+    say("ar ll", name)
+    cfg = get_config(name, ll_ar=1)
+    model, w = model_for(cfg)
+    x = gradient_noise_image(H, W, seed=1)[None] if N == 1 else sinusoid_1f_planes(H, W, planes=N, seed=2)
+    qs, _ = O.quantize(O.analyze(x, cfg, w), cfg)
+    ws = codec.Workspace(model, N, H, W)
+    got = codec.ar_params(model, q_to_device(qs), ws).cpu().numpy()
+    ref = O.ar_params(qs[0], cfg, w)
+    assert param_err(got, ref, 3) <= PARAM_RTOL
+    check_cdf_rows(codec.cdf_tables(model, torch.from_numpy(got).cuda()).cpu().numpy().view(np.uint16),
+                   got, cfg)
+    data, q_enc = codec.encode(model, x)
+    xh, _, q_dec = codec.decode(model, data)
+    assert torch.equal(q_enc, q_dec)
+    # A corrupted LL stream is reported through the kernel's status word.
+    N_, H_, W_, streams = codec.unpack_stream(model, data)
+    bad = [s.copy() if isinstance(s, list) else s for s in streams]
+    ll = bytearray(bad[0][0][0])
+    ll[len(ll) // 2] ^= 0xA5
+    q = torch.zeros_like(q_enc)
+    with pytest.raises(L.WvError):
+        codec.ar_decode(model, q, codec.Workspace(model, N, H, W), [bytes(ll)] + [s[0][0] for s in bad[1:]])

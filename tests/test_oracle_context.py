@@ -201,3 +201,45 @@ def test_block_architecture_residual_paths_and_causality():
     pert[i] = np.where(gm[None] >= g, np.clip(qs[i] + 9, -64, 64), qs[i])
     got = O.step_params(pert[i], O.long_context(pert, cfg, w, upto=i + 1)[i], 1, g, cfg, w)
     assert np.array_equal(got, ref[i][g])
+
+
+def test_ar_ll_model_causal_taps_and_brute_force():
+    from wvgen import get_config, make_weights
+    cfg = get_config("gray64", ll_ar=1)
+    w = make_weights(cfg)
+    assert len(O.AR_TAPS) == 12
+    assert all(dy < 0 or (dy == 0 and dx < 0) for dy, dx in O.AR_TAPS)     # strictly causal
+    rng = np.random.default_rng(17)
+    q = rng.integers(-6, 7, (1, 5, 7))
+    p = O.ar_params(q, cfg, w)
+    # Brute force: one position's parameters from an explicit loop over its neighbours.
+    r, c = 3, 4
+    W0, b0 = w["ar.0.w"].astype(np.float64), w["ar.0.b"].astype(np.float64)
+    a = b0.copy()
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            if (dy, dx) in O.AR_TAPS and 0 <= r + dy < 5 and 0 <= c + dx < 7:
+                a += W0[:, 0, dy + 2, dx + 2] * q[0, r + dy, c + dx]
+    a = np.maximum(a, 0)
+    a = np.maximum(w["ar.1.w"][:, :, 0, 0].astype(np.float64) @ a + w["ar.1.b"], 0)
+    raw = w["ar.2.w"][:, :, 0, 0].astype(np.float64) @ a + w["ar.2.b"]
+    np.testing.assert_allclose(p[0, r * 7 + c], O.mixture_head(raw[None], cfg)[0], atol=1e-12)
+    # Causality: changing the symbol at raster position k only affects positions after k.
+    k = 17
+    q2 = q.copy()
+    q2.reshape(-1)[k] += 5
+    p2 = O.ar_params(q2, cfg, w)
+    assert np.array_equal(p2[0, :k + 1], p[0, :k + 1])
+    assert not np.array_equal(p2[0, k + 1:], p[0, k + 1:])
+
+
+def test_ar_ll_oracle_roundtrip(cfg_small):
+    from wvgen import get_config, make_weights
+    cfg = get_config("gray64", ll_ar=1)
+    w = make_weights(cfg)
+    x = gradient_noise_image(64, 64, seed=1)[None]
+    streams, qs, _ = O.encode(x, cfg, w)
+    assert streams[0][0][1:] == [b"", b"", b""]
+    xr, qd = O.decode(streams, cfg, w, 64, 64, 1)
+    for a, b in zip(qs, qd):
+        assert np.array_equal(a, b)

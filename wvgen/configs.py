@@ -11,6 +11,8 @@ _BASE = dict(
     mix_k=3,            # mixture components per coefficient
     dist="gauss",       # component family: "gauss" or "laplace"
     ctx_arch="plain",   # step stacks: "plain" conv stacks or "blocks" (DepthConv / Residual)
+    ll_ar=0,            # 1: LL_J coded autoregressively (raster order) instead of in four steps
+    ar_ch=32,           # channels of the autoregressive LL model
     sym_min=-64,        # symbol alphabet [sym_min, sym_max]
     sym_max=64,
     cdf_bits=16,        # CDF tables are 16-bit integers summing to 2**cdf_bits

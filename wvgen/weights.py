@@ -18,6 +18,9 @@ Manifest order:
      for g = 0 a DepthConvBlock p1a (1x1), dw (depth-wise 3x3, weight
      [C][1][3][3]), p1b (1x1), p2a (1x1), p2b (1x1), for g >= 1 a Residual
      Block ra, rb (3x3), then out (3x3, C -> 3K).
+  4. with ll_ar: the autoregressive LL model ar.0 (5x5, 1 -> ar_ch, of which
+     only the 12 causal taps are used), ar.1 (1x1, ar_ch -> ar_ch), ar.2
+     (1x1, ar_ch -> 3*mix_k).
 """
 import numpy as np
 
@@ -71,6 +74,11 @@ def manifest(cfg):
                 conv(pre + ".ra", C, C)
                 conv(pre + ".rb", C, C)
             conv(pre + ".out", C, 3 * cfg["mix_k"])
+    if cfg.get("ll_ar", 0):
+        A = cfg.get("ar_ch", 32)
+        conv("ar.0", 1, A, 5)                 # masked 5x5: only the 12 causal taps are used
+        conv("ar.1", A, A, 1)
+        conv("ar.2", A, 3 * cfg["mix_k"], 1)
     return out
 
 
