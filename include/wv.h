@@ -219,6 +219,43 @@ int wv_ar_params(const wv_model* m, const int16_t* d_q, int nplanes, int H, int 
 int wv_ar_decode(const wv_model* m, const uint8_t* d_bytes, const long long* d_offsets,
                  int nplanes, int H, int W, int16_t* d_q, int* d_status, void* stream);
 
+/*
+ * Plans: several groups of planes of different sizes decoded together, each
+ * layer of a coding step running as ONE persistent launch over all groups
+ * (a work list of per-group segments, walked with a static stride: no
+ * atomics, results bit-identical to the per-group calls).  A group is
+ * nplanes planes of H x W with its own symbols and workspace, exactly the
+ * buffers wv_context_params would take for it.  Segment descriptors for
+ * every layer of every step are built once, on the host, and uploaded into
+ * d_desc; afterwards a step launches with no copies, so a whole decode can be
+ * captured in a graph and replayed.  Needs ctx_arch 0.
+ *   nb_table: optional [levels] output-channel blocks per workgroup (1, 2, 4)
+ *             of the inner layers of level j subbands, from an autotuner;
+ *             NULL picks by occupancy.  The choice does not change results.
+ *   wv_plan_bytes: descriptor bytes, and the largest row count of a step.
+ *   wv_plan_create: d_params float [max_rows][3K]: the parameters of one
+ *             step, group after group (group b from row group_first[b]).
+ *   wv_plan_rows: rows of step (subband, step) and each group's first row.
+ *   wv_plan_context_params: as wv_context_params for every group.
+ *   wv_plan_scatter: d_sym uint8 laid out like the parameters' rows.
+ */
+typedef struct wv_group {
+    int H, W, nplanes;
+    int16_t* d_q;     /* [nplanes][H*W] */
+    float* d_state;   /* wv_workspace_bytes(state) for this group */
+    void* d_scratch;  /* wv_workspace_bytes(scratch) for this group */
+} wv_group;
+typedef struct wv_plan wv_plan;
+
+int wv_plan_bytes(const wv_model* m, int ngroups, const wv_group* groups, const int* nb_table,
+                  size_t* desc_bytes, long long* max_rows);
+int wv_plan_create(const wv_model* m, int ngroups, const wv_group* groups, const int* nb_table,
+                   void* d_desc, size_t desc_bytes, float* d_params, void* stream, wv_plan** out);
+void wv_plan_destroy(wv_plan* p);
+int wv_plan_rows(const wv_plan* p, int subband, int step, long long* rows, long long* group_first);
+int wv_plan_context_params(const wv_plan* p, int subband, int step, void* stream);
+int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int subband, int step, void* stream);
+
 /* Write decoded symbol indices (symbol - sym_min) of step `step` of subband
  * `subband` into the packed symbols: d_sym uint8 [nplanes][n_g]. */
 int wv_scatter_symbols(const wv_config* cfg, const uint8_t* d_sym, int nplanes, int H, int W,

@@ -35,6 +35,11 @@ class wv_config(ctypes.Structure):
                 ("ctx_arch", ctypes.c_int), ("ll_ar", ctypes.c_int), ("ar_ch", ctypes.c_int)]
 
 
+class wv_group(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("nplanes", ctypes.c_int),
+                ("d_q", ctypes.c_void_p), ("d_state", ctypes.c_void_p), ("d_scratch", ctypes.c_void_p)]
+
+
 class wv_subband(ctypes.Structure):
     _fields_ = [("h", ctypes.c_int), ("w", ctypes.c_int), ("level", ctypes.c_int),
                 ("type", ctypes.c_int), ("offset", ctypes.c_longlong)]
@@ -62,6 +67,12 @@ _SIGS = {
     "wv_cdf_tables": (_I, [_P, _LL, _I, _I, _I, _I, _I, _P, _P]),
     "wv_ar_params": (_I, [_P, _P, _I, _I, _I, _P, _P]),
     "wv_ar_decode": (_I, [_P, _P, _P, _I, _I, _I, _P, _P, _P]),
+    "wv_plan_bytes": (_I, [_P, _I, _P, _P, ctypes.POINTER(_SZ), ctypes.POINTER(_LL)]),
+    "wv_plan_create": (_I, [_P, _I, _P, _P, _P, _SZ, _P, _P, ctypes.POINTER(_P)]),
+    "wv_plan_destroy": (None, [_P]),
+    "wv_plan_rows": (_I, [_P, _I, _I, ctypes.POINTER(_LL), _P]),
+    "wv_plan_context_params": (_I, [_P, _I, _I, _P]),
+    "wv_plan_scatter": (_I, [_P, _P, _I, _I, _P]),
     "wv_scatter_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_gather_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_synthesize": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P]),

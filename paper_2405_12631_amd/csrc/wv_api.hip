@@ -1092,3 +1092,261 @@ extern "C" int wv_temporal_haar_forward(float* f, int T, long long n, void* stre
 extern "C" int wv_temporal_haar_inverse(float* f, int T, long long n, void* stream) {
     return thaar(f, T, n, 1, stream);
 }
+
+// ---------------------------------------------------------------------------
+// plans: several plane groups of different sizes, one launch per layer
+// ---------------------------------------------------------------------------
+namespace {
+struct PlanLaunch {
+    size_t seg_off;      // byte offset of this launch's segment array in the descriptor buffer
+    int nseg, mode, nb, grid;
+    long long total;     // work items
+    MfmaLayer proto;
+    MfmaLayer16 proto16;
+};
+}  // namespace
+
+struct wv_plan {
+    const wv_model* m;
+    std::vector<wv_group> groups;
+    std::vector<std::vector<Sub>> lay;            // per group
+    std::vector<std::vector<PlanLaunch>> steps;   // [subband * 4 + step] -> launches
+    std::vector<std::vector<long long>> row_off;  // [subband * 4 + step] -> per group first row, + total
+    char* d_desc;
+    float* d_params;
+};
+
+static int plan_build(const wv_model* m, int ng, const wv_group* groups, const int* nb_table,
+                      std::vector<char>& host, wv_plan* P) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (ng < 1 || !groups) return fail(WV_EINVAL, "no groups");
+    if (m->cfg.ctx_arch != 0) return fail(WV_EUNSUPPORTED, "plans need ctx_arch 0");
+    const bool bf16 = m->precision == WV_BF16;
+    const int C = m->cfg.ctx_ch;
+    const int J = m->cfg.levels;
+    const int nsub = 3 * J + 1;
+    const int th = conv_tile_h(bf16), tw = conv_tile_w(bf16);
+    P->m = m;
+    P->groups.assign(groups, groups + ng);
+    P->lay.resize(ng);
+    for (int b = 0; b < ng; ++b) {
+        if (groups[b].nplanes < 1) return fail(WV_ESHAPE, "group %d has no planes", b);
+        int rc = layout(m->cfg, groups[b].H, groups[b].W, P->lay[b]);
+        if (rc) return rc;
+    }
+    P->steps.assign(nsub * 4, {});
+    P->row_off.assign(nsub * 4, {});
+    host.clear();
+    const int seg_size = bf16 ? (int)sizeof(ConvSeg16) : (int)sizeof(ConvSeg);
+    for (int i = 0; i < nsub; ++i) {
+        for (int g = 0; g < 4; ++g) {
+            std::vector<long long>& ro = P->row_off[i * 4 + g];
+            long long rows = 0;
+            for (int b = 0; b < ng; ++b) {
+                ro.push_back(rows);
+                rows += (long long)groups[b].nplanes * wv_group_count(P->lay[b][i].h, P->lay[b][i].w, g);
+            }
+            ro.push_back(rows);
+            const int type = P->lay[0][i].type;
+            const int level = P->lay[0][i].level;
+            const int nlayers = (int)(bf16 ? m->ctx16[type][g].size() : m->ctx[type][g].size());
+            // launch list: LSTM at step 0, then the stack's layers
+            for (int l = (g == 0 ? -1 : 0); l < nlayers; ++l) {
+                const bool lstm = l < 0;
+                const bool last = l == nlayers - 1;
+                const int mode = lstm ? CONV_LSTM : (last ? CONV_HEAD : CONV_RELU);
+                const MfmaLayer* L32 = bf16 ? nullptr : (lstm ? &m->lstm : &m->ctx[type][g][l]);
+                const MfmaLayer16* L16 = bf16 ? (lstm ? &m->lstm16 : &m->ctx16[type][g][l]) : nullptr;
+                const int nbt = bf16 ? L16->nbt : L32->nbt;
+                long long tiles = 0;
+                for (int b = 0; b < ng; ++b) {
+                    const Sub& S = P->lay[b][i];
+                    tiles += (long long)((S.w + tw - 1) / tw) * ((S.h + th - 1) / th) * groups[b].nplanes;
+                }
+                int nb = conv_pick_nb(nbt, mode, tiles);
+                if (nb_table && mode == CONV_RELU) {
+                    const int want = nb_table[level - 1];
+                    if (want == 1 || want == 2 || want == 4) nb = want <= nbt ? want : nbt;
+                }
+                PlanLaunch pl{};
+                pl.seg_off = host.size();
+                pl.nseg = ng;
+                pl.mode = mode;
+                pl.nb = nb;
+                if (bf16) pl.proto16 = *L16; else pl.proto = *L32;
+                long long item = 0;
+                for (int b = 0; b < ng; ++b) {
+                    const wv_group& G = groups[b];
+                    const Sub& S = P->lay[b][i];
+                    const long long HW = (long long)G.H * G.W;
+                    const size_t SS = state_floats(m->cfg, G.nplanes, G.H, G.W);
+                    float* hcur = G.d_state + (size_t)(i & 1) * 2 * SS;
+                    const long long st_ps = (long long)S.h * S.w * C;
+                    const Scratch sc = scratch_layout(m->cfg, G.nplanes, G.H, G.W);
+                    float* act[2] = {(float*)G.d_scratch + sc.act0, (float*)G.d_scratch + sc.act1};
+                    ConvArgs a{};
+                    a.N = G.nplanes;
+                    a.h = S.h;
+                    a.w = S.w;
+                    a.tiles_x = (S.w + tw - 1) / tw;
+                    a.tiles_y = (S.h + th - 1) / th;
+                    if (lstm) {
+                        a.sym_step = 4;
+                        a.h_out = hcur;
+                        a.c_out = hcur + SS;
+                        a.st_ps = st_ps;
+                        a.C = C;
+                        if (i > 0) {
+                            const Sub& Pv = P->lay[b][i - 1];
+                            const int up = (S.h == 2 * Pv.h) ? 1 : 0;
+                            float* hold = G.d_state + (size_t)((i - 1) & 1) * 2 * SS;
+                            a.in = hold;
+                            a.in_ps = (long long)Pv.h * Pv.w * C;
+                            a.in_up = up;
+                            a.sym = G.d_q + Pv.off;
+                            a.sym_ps = HW;
+                            a.sym_up = up;
+                            a.c_prev = hold + SS;
+                            a.cprev_ps = (long long)Pv.h * Pv.w * C;
+                            a.cprev_up = up;
+                        }
+                        if (bf16) {
+                            a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+                            a.in = nullptr;
+                            a.h16_out = reinterpret_cast<uint16_t*>(hcur);
+                            a.h_out = nullptr;
+                        }
+                    } else {
+                        a.in = l == 0 ? hcur : act[(l - 1) & 1];
+                        a.in_ps = st_ps;
+                        if (l == 0 && g > 0) {
+                            a.sym = G.d_q + S.off;
+                            a.sym_ps = HW;
+                            a.sym_step = g;
+                        }
+                        if (!last) {
+                            a.out = act[l & 1];
+                            a.out_ps = st_ps;
+                            a.out_cs = C;
+                        } else {
+                            a.params = P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr;
+                            a.step = g;
+                            a.K = m->cfg.mix_k;
+                            a.sigma_min = m->cfg.sigma_min;
+                        }
+                        if (bf16) {
+                            a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+                            a.in = nullptr;
+                            a.out16 = reinterpret_cast<uint16_t*>(a.out);
+                            a.out = nullptr;
+                        }
+                    }
+                    const long long items = (long long)a.tiles_x * a.tiles_y * a.N * (mode == CONV_HEAD ? 1 : nbt / nb);
+                    const size_t at = host.size();
+                    host.resize(at + seg_size);
+                    if (bf16) {
+                        ConvSeg16 sg{*L16, a, item};
+                        memcpy(host.data() + at, &sg, sizeof sg);
+                    } else {
+                        ConvSeg sg{*L32, a, item};
+                        memcpy(host.data() + at, &sg, sizeof sg);
+                    }
+                    item += items;
+                }
+                pl.total = item;
+                pl.grid = (int)(item < 1024 ? item : 1024);
+                P->steps[i * 4 + g].push_back(pl);
+                host.resize((host.size() + 255) & ~(size_t)255);
+            }
+        }
+    }
+    return WV_OK;
+}
+
+extern "C" int wv_plan_bytes(const wv_model* m, int ngroups, const wv_group* groups,
+                             const int* nb_table, size_t* desc_bytes, long long* max_rows) {
+    wv_plan P{};
+    P.d_params = nullptr;
+    std::vector<char> host;
+    int rc = plan_build(m, ngroups, groups, nb_table, host, &P);
+    if (rc) return rc;
+    if (desc_bytes) *desc_bytes = host.size();
+    if (max_rows) {
+        long long mx = 0;
+        for (auto& ro : P.row_off) mx = ro.back() > mx ? ro.back() : mx;
+        *max_rows = mx;
+    }
+    return WV_OK;
+}
+
+extern "C" int wv_plan_create(const wv_model* m, int ngroups, const wv_group* groups,
+                              const int* nb_table, void* d_desc, size_t desc_bytes, float* d_params,
+                              void* stream, wv_plan** out) {
+    if (!d_desc || !d_params || !out) return fail(WV_EINVAL, "null pointer");
+    wv_plan* P = new wv_plan();
+    P->d_params = d_params;
+    std::vector<char> host;
+    int rc = plan_build(m, ngroups, groups, nb_table, host, P);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    if (host.size() > desc_bytes) {
+        delete P;
+        return fail(WV_ENOMEM, "descriptor buffer has %zu bytes, needs %zu", desc_bytes, host.size());
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(d_desc, host.data(), host.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete P;
+        return fail(WV_EDEVICE, "descriptor upload failed: %s", hipGetErrorString(e));
+    }
+    P->d_desc = (char*)d_desc;
+    *out = P;
+    return WV_OK;
+}
+
+extern "C" void wv_plan_destroy(wv_plan* p) { delete p; }
+
+extern "C" int wv_plan_rows(const wv_plan* p, int i, int g, long long* rows, long long* group_first) {
+    if (!p || !rows) return fail(WV_EINVAL, "null pointer");
+    const int nsub = (int)p->lay[0].size();
+    if (i < 0 || i >= nsub || g < 0 || g > 3) return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    const auto& ro = p->row_off[i * 4 + g];
+    *rows = ro.back();
+    if (group_first)
+        for (size_t b = 0; b + 1 < ro.size(); ++b) group_first[b] = ro[b];
+    return WV_OK;
+}
+
+extern "C" int wv_plan_context_params(const wv_plan* p, int i, int g, void* stream) {
+    if (!p) return fail(WV_EINVAL, "null plan");
+    const int nsub = (int)p->lay[0].size();
+    if (i < 0 || i >= nsub || g < 0 || g > 3) return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    hipStream_t s = (hipStream_t)stream;
+    const bool bf16 = p->m->precision == WV_BF16;
+    for (const PlanLaunch& pl : p->steps[i * 4 + g]) {
+        if (bf16)
+            HIPCHK(launch_conv_seg_bf16(reinterpret_cast<const ConvSeg16*>(p->d_desc + pl.seg_off), pl.nseg,
+                                        pl.total, pl.proto16, pl.mode, pl.nb, pl.grid, s));
+        else
+            HIPCHK(launch_conv_seg(reinterpret_cast<const ConvSeg*>(p->d_desc + pl.seg_off), pl.nseg, pl.total,
+                                   pl.proto, pl.mode, pl.nb, pl.grid, s));
+    }
+    return WV_OK;
+}
+
+extern "C" int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int i, int g, void* stream) {
+    if (!p || !d_sym) return fail(WV_EINVAL, "null pointer");
+    const int nsub = (int)p->lay[0].size();
+    if (i < 0 || i >= nsub || g < 0 || g > 3) return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    const auto& ro = p->row_off[i * 4 + g];
+    for (size_t b = 0; b < p->groups.size(); ++b) {
+        const wv_group& G = p->groups[b];
+        const Sub& S = p->lay[b][i];
+        HIPCHK(launch_scatter(d_sym + ro[b], G.d_q, G.nplanes, (long long)G.H * G.W, S.off, S.h, S.w, g,
+                              p->m->cfg.sym_min, (hipStream_t)stream));
+    }
+    return WV_OK;
+}

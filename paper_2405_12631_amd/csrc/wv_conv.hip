@@ -32,7 +32,8 @@ constexpr int HALO = HALO_H * HALO_W;
 __device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
 
 template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
+__device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs& a, const int tile_idx,
+                                              const int ycol) {
     // TAPS == 9: 3x3 conv; TAPS == 1: 1x1 conv (centre tap only, same data path).
     constexpr int STRIDE = CIN + 4;          // 68 floats for CIN = 64: conflict-free float4 reads
     constexpr int CB = CIN / 16;
@@ -51,14 +52,14 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int t = blockIdx.x;
+    int t = tile_idx;
     const int tx = t % a.tiles_x;
     t /= a.tiles_x;
     const int ty = t % a.tiles_y;
     const int n = t / a.tiles_y;
     const int r0 = ty * TILE_H;
     const int c0 = tx * TILE_W;
-    const int nblk0 = blockIdx.y * NB;
+    const int nblk0 = ycol * NB;
     const int row0 = wave * 2 + (MODE == CONV_HEAD ? (a.step >> 1) : 0);   // first tile row of this wave
 
     // B fragments of one tap for blocks [nblk0, nblk0 + NB): global [tap][cb][nbt][64][4].
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
     // ---- epilogues.  Lane holds D[4*(lane/16) + i][lane % 16] of each block. ----
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
-    if (MODE == CONV_RELU || MODE == CONV_TANH || MODE == CONV_RES) {
+    if constexpr (MODE == CONV_RELU || MODE == CONV_TANH || MODE == CONV_RES) {
         // Stage the output tile [128 positions][16 NB channels] in LDS (reusing the
         // halo buffer), then write float4 chunks: full, coalesced lines.  CONV_RES
         // adds the skip tensor (same layout as the output) while storing.
@@ -248,10 +249,10 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                 *reinterpret_cast<float4*>(a.out + o) = v;
             }
         }
-    } else if (MODE == CONV_LSTM) {
+    } else if constexpr (MODE == CONV_LSTM) {
         // Block nb of this workgroup is gate nb (input, forget, cell, output)
-        // of channels 16*blockIdx.y .. +15 (the packer orders the columns so).
-        const int ch = blockIdx.y * 16 + col;
+        // of channels 16*ycol .. +15 (the packer orders the columns so).
+        const int ch = ycol * 16 + col;
         const float bi = L.bias[(nblk0 + 0) * 16 + col];
         const float bf = L.bias[(nblk0 + 1) * 16 + col];
         const float bg = L.bias[(nblk0 + 2) * 16 + col];
@@ -301,6 +302,32 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
                 mixture_head(v, K, a.sigma_min, o);
             }
         }
+    }
+}
+
+template <int CIN, int NB, bool SYM, int MODE, int TAPS>
+__global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
+    conv_tile_f32<CIN, NB, SYM, MODE, TAPS>(L, a, blockIdx.x, blockIdx.y);
+}
+
+// Persistent form: a fixed grid walks the work items of several segments (each
+// its own planes, sizes, buffers and weights), item = blockIdx.x + k gridDim.x.
+// Segment s covers items [item0, item0 + tiles * columns); its item i is tile
+// i % tiles of column i / tiles.  Static assignment: no atomics, same bits.
+template <int CIN, int NB, bool SYM, int MODE, int TAPS>
+__global__ __launch_bounds__(256) void conv3x3_mfma_f32_seg(const ConvSeg* __restrict__ segs, int nseg,
+                                                    long long total) {
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        int lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].item0 <= it) lo = mid; else hi = mid;
+        }
+        const ConvSeg& S = segs[lo];
+        const long long local = it - S.item0;
+        const long long ntiles = (long long)S.a.tiles_x * S.a.tiles_y * S.a.N;
+        conv_tile_f32<CIN, NB, SYM, MODE, TAPS>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
+        __syncthreads();
     }
 }
 
@@ -361,7 +388,67 @@ hipError_t dispatch_nb(const MfmaLayer& L, int mode, int taps, const ConvArgs& a
     return hipErrorInvalidValue;
 }
 
+template <int CIN, int NB, bool SYM, int MODE, int TAPS = 9>
+hipError_t seg_t(const ConvSeg* segs, int nseg, long long total, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((conv3x3_mfma_f32_seg<CIN, NB, SYM, MODE, TAPS>), dim3(grid), dim3(256), 0, s, segs,
+                       nseg, total);
+    return hipGetLastError();
+}
+
+template <int CIN, int NB, bool SYM>
+hipError_t seg_mode(const ConvSeg* segs, int nseg, long long total, int mode, int taps, int grid,
+                    hipStream_t s) {
+    if (taps == 1) {
+        if (SYM) return hipErrorInvalidValue;
+        switch (mode) {
+            case CONV_RELU: return seg_t<CIN, NB, false, CONV_RELU, 1>(segs, nseg, total, grid, s);
+            case CONV_RES: return seg_t<CIN, NB, false, CONV_RES, 1>(segs, nseg, total, grid, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    switch (mode) {
+        case CONV_RELU: return seg_t<CIN, NB, SYM, CONV_RELU>(segs, nseg, total, grid, s);
+        case CONV_RES: return SYM ? hipErrorInvalidValue : seg_t<CIN, NB, false, CONV_RES>(segs, nseg, total, grid, s);
+        case CONV_LSTM: return NB == 4 ? seg_t<CIN, 4, SYM, CONV_LSTM>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+        case CONV_HEAD: return NB == 1 ? seg_t<CIN, 1, SYM, CONV_HEAD>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int CIN>
+hipError_t seg_nb(const ConvSeg* segs, int nseg, long long total, int sym, int mode, int taps, int nb,
+                  int grid, hipStream_t s) {
+#define WV_SEG_NB(NBV)                                                                   \
+    if (nb == NBV) return sym ? seg_mode<CIN, NBV, true>(segs, nseg, total, mode, taps, grid, s) \
+                              : seg_mode<CIN, NBV, false>(segs, nseg, total, mode, taps, grid, s);
+    WV_SEG_NB(1) WV_SEG_NB(2) WV_SEG_NB(4)
+#undef WV_SEG_NB
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+int conv_pick_nb(int nbt, int mode, long long tiles) {
+    if (mode == CONV_HEAD) return 1;
+    if (mode == CONV_LSTM) return 4;
+    int nb = nbt >= 4 ? 4 : nbt;
+    while (nb > 1 && tiles * (nbt / nb) < 512) nb >>= 1;
+    return nb;
+}
+int conv_tile_h(int bf16) { return bf16 ? 16 : TILE_H; }
+int conv_tile_w(int bf16) { return bf16 ? 16 : TILE_W; }
+
+hipError_t launch_conv_seg(const ConvSeg* segs, int nseg, long long total, const MfmaLayer& proto,
+                           int mode, int nb, int grid, hipStream_t s) {
+    if (total <= 0 || nseg <= 0) return hipSuccess;
+    const int taps = proto.taps == 1 ? 1 : 9;
+    switch (proto.cin) {
+        case 16: return seg_nb<16>(segs, nseg, total, proto.has_sym, mode, taps, nb, grid, s);
+        case 32: return seg_nb<32>(segs, nseg, total, proto.has_sym, mode, taps, nb, grid, s);
+        case 64: return seg_nb<64>(segs, nseg, total, proto.has_sym, mode, taps, nb, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s) {
     if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;

@@ -36,7 +36,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 template <int CIN, int NB, bool SYM, int MODE>
-__global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
+__device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvArgs& a, const int tile_idx,
+                                               const int ycol) {
     constexpr int STRIDE = CIN + 8;          // bf16 elements per halo position (conflict-free)
     constexpr int CC = CIN / 32;             // 32-channel K chunks per tap
     constexpr int BV = CC * NB * 64;         // uint4 of B per tap for this workgroup
@@ -54,14 +55,14 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, co
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int t = blockIdx.x;
+    int t = tile_idx;
     const int tx = t % a.tiles_x;
     t /= a.tiles_x;
     const int ty = t % a.tiles_y;
     const int n = t / a.tiles_y;
     const int r0 = ty * TH;
     const int c0 = tx * TW;
-    const int nblk0 = blockIdx.y * NB;
+    const int nblk0 = ycol * NB;
     // Rows of this wave: 4w .. 4w+3; the head keeps the two of parity step/2.
     const int gr = a.step >> 1;
 
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, co
 
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
-    if (MODE == CONV_RELU || MODE == CONV_TANH) {
+    if constexpr (MODE == CONV_RELU || MODE == CONV_TANH) {
         // Stage the output tile [256 positions][16 NB channels] in LDS (reusing the
         // halo buffer), then write 16-byte chunks: full, coalesced lines.
         constexpr int OS = NB * 16 + 8;
@@ -219,8 +220,8 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, co
                                           ((long long)r * a.w + c) * a.out_cs + nblk0 * 16 + c8 * 8) =
                     *reinterpret_cast<const uint4*>(lds_in + pos * OS + c8 * 8);
         }
-    } else if (MODE == CONV_LSTM) {
-        const int ch = blockIdx.y * 16 + col;
+    } else if constexpr (MODE == CONV_LSTM) {
+        const int ch = ycol * 16 + col;
         const float bi = L.bias[(nblk0 + 0) * 16 + col];
         const float bf = L.bias[(nblk0 + 1) * 16 + col];
         const float bg = L.bias[(nblk0 + 2) * 16 + col];
@@ -275,6 +276,29 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, co
 }
 
 template <int CIN, int NB, bool SYM, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
+    conv_tile_bf16<CIN, NB, SYM, MODE>(L, a, blockIdx.x, blockIdx.y);
+}
+
+// Persistent multi-segment form (see the FP32 kernel).
+template <int CIN, int NB, bool SYM, int MODE>
+__global__ __launch_bounds__(256) void conv3x3_mfma_bf16_seg(const ConvSeg16* __restrict__ segs, int nseg,
+                                                     long long total) {
+    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
+        int lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].item0 <= it) lo = mid; else hi = mid;
+        }
+        const ConvSeg16& S = segs[lo];
+        const long long local = it - S.item0;
+        const long long ntiles = (long long)S.a.tiles_x * S.a.tiles_y * S.a.N;
+        conv_tile_bf16<CIN, NB, SYM, MODE>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
+        __syncthreads();
+    }
+}
+
+template <int CIN, int NB, bool SYM, int MODE>
 hipError_t launch_t(const MfmaLayer16& L, const ConvArgs& a0, hipStream_t s) {
     ConvArgs a = a0;
     a.tiles_x = (a.w + TW - 1) / TW;
@@ -320,7 +344,45 @@ hipError_t dispatch_nb(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStr
     return hipErrorInvalidValue;
 }
 
+template <int CIN, int NB, bool SYM, int MODE>
+hipError_t seg_t(const ConvSeg16* segs, int nseg, long long total, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((conv3x3_mfma_bf16_seg<CIN, NB, SYM, MODE>), dim3(grid), dim3(256), 0, s, segs, nseg,
+                       total);
+    return hipGetLastError();
+}
+
+template <int CIN, int NB, bool SYM>
+hipError_t seg_mode(const ConvSeg16* segs, int nseg, long long total, int mode, int grid, hipStream_t s) {
+    switch (mode) {
+        case CONV_RELU: return seg_t<CIN, NB, SYM, CONV_RELU>(segs, nseg, total, grid, s);
+        case CONV_LSTM: return NB == 4 ? seg_t<CIN, 4, SYM, CONV_LSTM>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+        case CONV_HEAD: return NB == 1 ? seg_t<CIN, 1, SYM, CONV_HEAD>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int CIN>
+hipError_t seg_nb(const ConvSeg16* segs, int nseg, long long total, int sym, int mode, int nb, int grid,
+                  hipStream_t s) {
+#define WV_SEG_NB(NBV)                                                                   \
+    if (nb == NBV) return sym ? seg_mode<CIN, NBV, true>(segs, nseg, total, mode, grid, s) \
+                              : seg_mode<CIN, NBV, false>(segs, nseg, total, mode, grid, s);
+    WV_SEG_NB(1) WV_SEG_NB(2) WV_SEG_NB(4)
+#undef WV_SEG_NB
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total,
+                                const MfmaLayer16& proto, int mode, int nb, int grid, hipStream_t s) {
+    if (total <= 0 || nseg <= 0) return hipSuccess;
+    switch (proto.cin) {
+        case 32: return seg_nb<32>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
+        case 64: return seg_nb<64>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
     if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;

@@ -95,9 +95,32 @@ struct ConvArgs {
     float sigma_min;
 };
 
+// One segment of a persistent multi-segment conv launch: its own layer (weights),
+// arguments and first work item (items = tiles * columns of 16 NB channels).
+struct ConvSeg {
+    MfmaLayer L;
+    ConvArgs a;
+    long long item0;
+};
+struct ConvSeg16 {
+    MfmaLayer16 L;
+    ConvArgs a;
+    long long item0;
+};
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s);
+// Persistent launches over device segment arrays.  `proto` gives the template
+// shape shared by every segment (cin, has_sym, taps); nb output blocks per item.
+hipError_t launch_conv_seg(const ConvSeg* segs, int nseg, long long total, const MfmaLayer& proto,
+                           int mode, int nb, int grid, hipStream_t s);
+hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total,
+                                const MfmaLayer16& proto, int mode, int nb, int grid, hipStream_t s);
+// Output blocks per workgroup chosen for a launch of `tiles` position tiles.
+int conv_pick_nb(int nbt, int mode, long long tiles);
+int conv_tile_h(int bf16);
+int conv_tile_w(int bf16);
 
 // Lifting filter pieces.
 //   first: a1[n][r][c][ch] = tanh(b[ch] + sum_tap w[tap][ch] z(n, r+dy-1, c+dx-1))

@@ -1,0 +1,97 @@
+"""Plans over images of uneven size, persistent launches and graph replay (needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(64, 96), (32, 48), (48, 80), (32, 48)]     # two images share a size; ragged subbands
+
+
+def _images(sizes, seed=11):
+    return [sinusoid_1f_planes(h, w, planes=3, seed=seed + k) for k, (h, w) in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_plan_params_equal_per_group_calls_bitwise(prec):
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16, WV_FP32
+    say("plan vs per-group", prec)
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)),
+                        precision=WV_BF16 if prec == "bf16" else WV_FP32)
+    imgs = _images(SIZES)
+    bt = B.Batch(model, SIZES, nb_table=[1, 2, 4, 1])
+    bt.load_images(imgs)
+    # Reference: each group on its own through wv_context_params.
+    refs = []
+    for b, w in enumerate(bt.ws):
+        ws = codec.Workspace(model, w.N, w.H, w.W)
+        refs.append((ws, bt.q[b].clone()))
+    K = cfg["mix_k"]
+    for i in range(bt.nsub):
+        for g in range(4):
+            got = bt.context_params(i, g).clone()
+            n, first = bt.rows(i, g)
+            for b, (ws, q) in enumerate(refs):
+                ref = codec.context_params(model, q, ws, i, g).reshape(-1)
+                lo = first[b] * 3 * K
+                assert torch.equal(got[lo:lo + ref.numel()], ref), (i, g, b)
+
+
+def test_graph_replay_matches_eager_every_time():
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16
+    say("graph replay")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    bt = B.Batch(model, SIZES)
+    bt.load_images(_images(SIZES, seed=21))
+    known = [q.clone() for q in bt.q]
+    syms = bt.known_symbols()
+    eager = [x.clone() for x in bt.decode_elided(syms)]
+    torch.cuda.synchronize()
+    graph = bt.capture(syms)
+    for rep in range(3):
+        for q in bt.q:                       # eager work between replays
+            q.fill_(7)
+        for x in bt.xhat:
+            x.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for b in range(len(bt.q)):
+            assert torch.equal(bt.q[b], known[b]), (rep, b)
+            assert torch.equal(bt.xhat[b], eager[b]), (rep, b)
+    # Autotuning keeps the bits.
+    tab, t = B.autotune(bt, syms, reps=1)
+    say("autotune", tab, t)
+    out = [x.clone() for x in bt.decode_elided(syms)]
+    torch.cuda.synchronize()
+    for b in range(len(out)):
+        assert torch.equal(out[b], eager[b])
+
+
+def test_batch_result_equals_single_image_decode():
+    """Each image decodes to the same bits alone and inside the mixed batch."""
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16
+    say("batch vs alone")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    imgs = _images(SIZES, seed=31)
+    bt = B.Batch(model, SIZES)
+    bt.load_images(imgs)
+    out = bt.decode_elided(bt.known_symbols())
+    torch.cuda.synchronize()
+    for k, (h, w) in enumerate(SIZES):
+        ws = codec.Workspace(model, 3, h, w)
+        q, _, _ = codec.analyze(model, torch.from_numpy(imgs[k]).cuda(), ws)
+        syms = codec.prepare_elided(model, q, ws)
+        q0 = torch.zeros_like(q)
+        alone = codec.decode_elided(model, syms, ws, q0)
+        gb, p0 = bt.where[k]
+        assert torch.equal(alone, out[gb][p0:p0 + 3]), k
