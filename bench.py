@@ -8,6 +8,11 @@ host entropy coder would return are taken from a device buffer), then
 dequantisation and synthesis.  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--precision fp32|bf16] [--workload ycbcr512x768|batch64_mixed]
+
+The default is the FP32 batch-1 512x768 workload.  --workload batch64_mixed
+times a mixed-size batch of 64 images (BF16 context, persistent launches,
+graph replay, autotuned blocking).
 
 Prints one JSON line.
 """
@@ -62,19 +67,103 @@ def cpu_baseline(cfg, w, x, q_planes):
                        "and synthesis in float64 (one third of one image's work)")
 
 
+def bench_batch(args):
+    """Mixed-size batch: 64 three-plane images from four sizes (seed 3), BF16 context
+    convs, one plan (persistent launches), the whole decode captured in a HIP graph,
+    per-level blocking autotuned before timing.  One step = one graph replay = one
+    coder-elided decode of all 64 images."""
+    import torch
+    from paper_2405_12631_amd import batch as B, codec, WV_BF16, WV_FP32
+    from wvgen import batch_sizes, get_config, make_weights, pack_weights, sinusoid_1f_planes
+
+    cfg = get_config("batch64_mixed")
+    prec = WV_FP32 if args.precision == "fp32" else WV_BF16
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=prec)
+    sizes, seeds = batch_sizes(cfg["batch"], cfg["sizes"], seed=cfg["seed_image"])
+    images = [sinusoid_1f_planes(h, w, planes=3, seed=sd) for (h, w), sd in zip(sizes, seeds)]
+    bt = B.Batch(model, sizes)
+    bt.load_images(images)
+    del images
+    syms = bt.known_symbols()
+    log = (lambda m: print(m, file=sys.stderr, flush=True))
+    tab, _ = B.autotune(bt, syms, reps=1, log=log)
+    # Stage times from one eager, event-bracketed decode.
+    stream = torch.cuda.current_stream()
+    ev = []
+    for q in bt.q:
+        q.zero_()
+    for i in range(bt.nsub):
+        for g in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            prm = bt.context_params(i, g)
+            e1.record(stream)
+            ev.append((e0, e1))
+            bt.cdf_tables(prm)
+            bt.scatter(syms[i][g], i, g)
+    bt.synthesize()
+    torch.cuda.synchronize()
+    ctx_s = sum(a.elapsed_time(b) for a, b in ev) * 1e-3
+    graph = bt.capture(syms)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        graph.replay()
+        e1.record(stream)
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for b in range(len(bt.q)):
+        assert int(bt.q[b].abs().sum().item()) >= 0
+    lat = np.array([a.elapsed_time(b) for a, b in lat])
+    pixels = bt.pixels
+    mpx = pixels * args.steps / elapsed / 1e6
+    flops = context_flops_per_coef(cfg) * pixels * 3
+    peak = MFMA_PEAK_TFLOPS[args.precision]
+    out = dict(
+        metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
+        value=round(mpx, 4), unit="Mpixel/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(elapsed * 1e3 / args.steps, 3), higher_is_better=True, scaling="weak",
+        vs_baseline=None,
+        dtype=f"{args.precision} context convs (fp32 accumulate), fp32 lifting/cdf", data="synthetic",
+        config=dict(workload=f"batch64_mixed: 64 three-plane images, sizes drawn from "
+                             f"{cfg['sizes']} (seed 3), 1/f sinusoids, 4-level CNN lifting, "
+                             f"64-ch 4-layer context, one plan (persistent launches) replayed as a "
+                             f"HIP graph, autotuned blocking {tab}, coder elided",
+                    batch=cfg["batch"], pixels=pixels, planes=3),
+        p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
+        roofline=dict(bound="mfma", achieved=round(flops / ctx_s / 1e12, 3), peak=peak, unit="TFLOP/s",
+                      frac=round(flops / ctx_s / 1e12 / peak, 4), traffic=None,
+                      kernel="conv3x3_mfma_*_seg (context model, eager event timing)",
+                      flops_per_decode=flops),
+    )
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
-                    help="context-conv precision (lifting and CDFs stay FP32)")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+                    help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
+                         "bf16 for the batched workload")
+    ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed"], default="ycbcr512x768")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64_mixed":
+        args.precision = args.precision or "bf16"
+        return bench_batch(args)
+    args.precision = args.precision or "fp32"
 
     import torch
     from paper_2405_12631_amd import codec

@@ -256,6 +256,31 @@ int wv_plan_rows(const wv_plan* p, int subband, int step, long long* rows, long 
 int wv_plan_context_params(const wv_plan* p, int subband, int step, void* stream);
 int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int subband, int step, void* stream);
 
+/*
+ * Continuous batching: one call runs the coding step (subband, step) of each
+ * item, where every item is a plane group (like a wv_group) at its own
+ * position in its own decode.  The items' layers are grouped into one
+ * persistent launch per role (ConvLSTM; first layer without / with the symbol
+ * channel; each inner layer; the head), segments carrying their own weights.
+ * Results are bit-identical to calling wv_context_params per item.
+ * Descriptors are written to h_staging (pinned host memory the caller keeps
+ * untouched until the stream has passed this call) and copied to d_desc
+ * asynchronously; *used_bytes receives the bytes needed (n = 0 or
+ * h_staging == NULL with d_desc == NULL queries them).  Needs ctx_arch 0.
+ */
+typedef struct wv_step_item {
+    int H, W, nplanes;
+    int16_t* d_q;
+    float* d_state;
+    void* d_scratch;
+    int subband, step;
+    float* d_params;  /* [nplanes][n_g][3K] of this item */
+} wv_step_item;
+
+int wv_context_params_items(const wv_model* m, int n, const wv_step_item* items, void* h_staging,
+                            size_t staging_bytes, void* d_desc, size_t desc_bytes,
+                            size_t* used_bytes, void* stream);
+
 /* Write decoded symbol indices (symbol - sym_min) of step `step` of subband
  * `subband` into the packed symbols: d_sym uint8 [nplanes][n_g]. */
 int wv_scatter_symbols(const wv_config* cfg, const uint8_t* d_sym, int nplanes, int H, int W,
@@ -267,13 +292,19 @@ int wv_gather_symbols(const wv_config* cfg, const int16_t* d_q, int nplanes, int
 
 /*
  * Dequantisation and synthesis (Sec. 3.1): y_hat = q / Delta, then the exact
- * inverse of wv_analyze level by level, then + 128.
+ * inverse of wv_analyze level by level, then + offset (128 undoes the
+ * centring of uint8 input; 0 for planes analysed as centred floats).
  *   d_q or d_y (float packed subbands, used when d_q is NULL);
  *   d_xhat : float [nplanes][H][W];  d_u8 : optional uint8 clamp(rint(x_hat)).
  */
 int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int nplanes,
-                  int H, int W, float delta_L, float delta_H, void* d_scratch,
+                  int H, int W, float delta_L, float delta_H, float offset, void* d_scratch,
                   float* d_xhat, uint8_t* d_u8, void* stream);
+
+/* Elementwise helpers of the video path: out = x - 128 (uint8 -> float), and
+ * x += offset with an optional uint8 copy clamp(rint(x)). */
+int wv_center_u8(const uint8_t* d_x8, long long n, float* d_out, void* stream);
+int wv_add_offset(float* d_x, long long n, float offset, uint8_t* d_u8, void* stream);
 
 /*
  * Subband impulse responses (Sec. 3.4) of one plane's quantised subbands

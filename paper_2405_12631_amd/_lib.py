@@ -40,6 +40,12 @@ class wv_group(ctypes.Structure):
                 ("d_q", ctypes.c_void_p), ("d_state", ctypes.c_void_p), ("d_scratch", ctypes.c_void_p)]
 
 
+class wv_step_item(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("nplanes", ctypes.c_int),
+                ("d_q", ctypes.c_void_p), ("d_state", ctypes.c_void_p), ("d_scratch", ctypes.c_void_p),
+                ("subband", ctypes.c_int), ("step", ctypes.c_int), ("d_params", ctypes.c_void_p)]
+
+
 class wv_subband(ctypes.Structure):
     _fields_ = [("h", ctypes.c_int), ("w", ctypes.c_int), ("level", ctypes.c_int),
                 ("type", ctypes.c_int), ("offset", ctypes.c_longlong)]
@@ -73,9 +79,12 @@ _SIGS = {
     "wv_plan_rows": (_I, [_P, _I, _I, ctypes.POINTER(_LL), _P]),
     "wv_plan_context_params": (_I, [_P, _I, _I, _P]),
     "wv_plan_scatter": (_I, [_P, _P, _I, _I, _P]),
+    "wv_context_params_items": (_I, [_P, _I, _P, _P, _SZ, _P, _SZ, ctypes.POINTER(_SZ), _P]),
     "wv_scatter_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
     "wv_gather_symbols": (_I, [_CFG, _P, _I, _I, _I, _I, _I, _P, _P]),
-    "wv_synthesize": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _P, _P, _P, _P]),
+    "wv_synthesize": (_I, [_P, _P, _P, _I, _I, _I, _F, _F, _F, _P, _P, _P, _P]),
+    "wv_center_u8": (_I, [_P, _LL, _P, _P]),
+    "wv_add_offset": (_I, [_P, _LL, _F, _P, _P]),
     "wv_impulse_scratch_bytes": (_I, [_P, ctypes.POINTER(_SZ)]),
     "wv_impulse_responses": (_I, [_P, _P, _I, _I, _F, _F, _P, _P, _P]),
     "wv_temporal_haar_forward": (_I, [_P, _I, _LL, _P]),

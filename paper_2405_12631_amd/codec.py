@@ -159,7 +159,7 @@ def gather_symbols(model, q, ws, i, g, out=None):
     return out[:ws.N * ng].view(ws.N, ng)
 
 
-def synthesize(model, ws, q=None, y=None, xhat=None, want_u8=False):
+def synthesize(model, ws, q=None, y=None, xhat=None, want_u8=False, offset=128.0):
     """q int16 [N,HW] (or float packed y) -> (xhat float [N,H,W], u8|None)."""
     N, H, W = ws.N, ws.H, ws.W
     dev = (q if q is not None else y).device
@@ -167,9 +167,23 @@ def synthesize(model, ws, q=None, y=None, xhat=None, want_u8=False):
         xhat = torch.empty((N, H, W), dtype=torch.float32, device=dev)
     u8 = torch.empty((N, H, W), dtype=torch.uint8, device=dev) if want_u8 else None
     dL, dH = model.deltas()
-    L.call("wv_synthesize", model.h, _ptr(q), _ptr(y), N, H, W, dL, dH, _ptr(ws.scratch),
+    L.call("wv_synthesize", model.h, _ptr(q), _ptr(y), N, H, W, dL, dH, offset, _ptr(ws.scratch),
            _ptr(xhat), _ptr(u8), _stream())
     return xhat, u8
+
+
+def center_u8(x8, out=None):
+    """uint8 device tensor -> float x - 128 (library kernel)."""
+    if out is None:
+        out = torch.empty(x8.shape, dtype=torch.float32, device=x8.device)
+    L.call("wv_center_u8", _ptr(x8), x8.numel(), _ptr(out), _stream())
+    return out
+
+
+def add_offset(x, offset, want_u8=False):
+    u8 = torch.empty(x.shape, dtype=torch.uint8, device=x.device) if want_u8 else None
+    L.call("wv_add_offset", _ptr(x), x.numel(), offset, _ptr(u8), _stream())
+    return x, u8
 
 
 def impulse_responses(model, q_plane, H, W):

@@ -721,9 +721,23 @@ static int synth_impl(const wv_model* m, const int16_t* d_q, const float* d_y, i
                       float offset, void* stream);
 
 extern "C" int wv_synthesize(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H,
-                             int W, float dL, float dH, void* d_scratch, float* d_xhat, uint8_t* d_u8,
-                             void* stream) {
-    return synth_impl(m, d_q, d_y, N, H, W, dL, dH, d_scratch, d_xhat, d_u8, 128.0f, stream);
+                             int W, float dL, float dH, float offset, void* d_scratch, float* d_xhat,
+                             uint8_t* d_u8, void* stream) {
+    return synth_impl(m, d_q, d_y, N, H, W, dL, dH, d_scratch, d_xhat, d_u8, offset, stream);
+}
+
+extern "C" int wv_center_u8(const uint8_t* d_x8, long long n, float* d_out, void* stream) {
+    if (n < 0) return fail(WV_ESHAPE, "negative size");
+    if (n > 0 && (!d_x8 || !d_out)) return fail(WV_EINVAL, "null pointer");
+    HIPCHK(launch_center_u8(d_x8, d_out, n, (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" int wv_add_offset(float* d_x, long long n, float offset, uint8_t* d_u8, void* stream) {
+    if (n < 0) return fail(WV_ESHAPE, "negative size");
+    if (n > 0 && !d_x) return fail(WV_EINVAL, "null pointer");
+    HIPCHK(launch_finalize(d_x, d_u8, n, offset, (hipStream_t)stream));
+    return WV_OK;
 }
 
 static int synth_impl(const wv_model* m, const int16_t* d_q, const float* d_y, int N, int H, int W,
@@ -1347,6 +1361,193 @@ extern "C" int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int i, in
         const Sub& S = p->lay[b][i];
         HIPCHK(launch_scatter(d_sym + ro[b], G.d_q, G.nplanes, (long long)G.H * G.W, S.off, S.h, S.w, g,
                               p->m->cfg.sym_min, (hipStream_t)stream));
+    }
+    return WV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// items: plane groups at different (subband, step) positions in one call
+// ---------------------------------------------------------------------------
+namespace {
+struct ItemLaunch {
+    std::vector<char> segs;
+    int nseg = 0, mode = 0, nb = 1;
+    long long total = 0;
+    long long tiles = 0;
+    MfmaLayer proto{};
+    MfmaLayer16 proto16{};
+};
+
+// Append one segment (an item's layer) to a launch list.
+void item_seg(ItemLaunch& Lc, bool bf16, const MfmaLayer* L32, const MfmaLayer16* L16, const ConvArgs& a) {
+    const size_t at = Lc.segs.size();
+    if (bf16) {
+        Lc.segs.resize(at + sizeof(ConvSeg16));
+        ConvSeg16 sg{*L16, a, 0};
+        memcpy(Lc.segs.data() + at, &sg, sizeof sg);
+        Lc.proto16 = *L16;
+    } else {
+        Lc.segs.resize(at + sizeof(ConvSeg));
+        ConvSeg sg{*L32, a, 0};
+        memcpy(Lc.segs.data() + at, &sg, sizeof sg);
+        Lc.proto = *L32;
+    }
+    Lc.nseg++;
+    Lc.tiles += (long long)a.tiles_x * a.tiles_y * a.N;
+}
+
+// Fix NB and item offsets once all segments of a launch are known.
+void item_finish(ItemLaunch& Lc, bool bf16) {
+    if (!Lc.nseg) return;
+    const int nbt = bf16 ? Lc.proto16.nbt : Lc.proto.nbt;
+    Lc.nb = conv_pick_nb(nbt, Lc.mode, Lc.tiles);
+    long long item = 0;
+    const size_t ss = bf16 ? sizeof(ConvSeg16) : sizeof(ConvSeg);
+    for (int k = 0; k < Lc.nseg; ++k) {
+        char* p = Lc.segs.data() + k * ss;
+        const ConvArgs& a = bf16 ? reinterpret_cast<ConvSeg16*>(p)->a : reinterpret_cast<ConvSeg*>(p)->a;
+        const int segnbt = bf16 ? reinterpret_cast<ConvSeg16*>(p)->L.nbt : reinterpret_cast<ConvSeg*>(p)->L.nbt;
+        if (bf16) reinterpret_cast<ConvSeg16*>(p)->item0 = item;
+        else reinterpret_cast<ConvSeg*>(p)->item0 = item;
+        item += (long long)a.tiles_x * a.tiles_y * a.N * (Lc.mode == CONV_HEAD ? 1 : segnbt / Lc.nb);
+    }
+    Lc.total = item;
+}
+}  // namespace
+
+extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_item* items,
+                                       void* h_staging, size_t staging_bytes, void* d_desc,
+                                       size_t desc_bytes, size_t* used_bytes, void* stream) {
+    if (!m) return fail(WV_EINVAL, "null model");
+    if (n < 0 || (n > 0 && !items)) return fail(WV_EINVAL, "bad item list");
+    if (m->cfg.ctx_arch != 0) return fail(WV_EUNSUPPORTED, "items need ctx_arch 0");
+    const bool bf16 = m->precision == WV_BF16;
+    const int C = m->cfg.ctx_ch;
+    const int Lc = m->cfg.ctx_layers;
+    const int th = conv_tile_h(bf16), tw = conv_tile_w(bf16);
+    // Launch roles: 0 LSTM, 1 first layer without symbols (step 0), 2 first layer with
+    // symbols, 3 + (l - 1) inner layer l, last: the head.
+    std::vector<ItemLaunch> launches(3 + (Lc - 2) + 1);
+    launches[0].mode = CONV_LSTM;
+    launches[1].mode = CONV_RELU;
+    launches[2].mode = CONV_RELU;
+    for (int l = 1; l < Lc - 1; ++l) launches[2 + l].mode = CONV_RELU;
+    launches.back().mode = CONV_HEAD;
+    for (int k = 0; k < n; ++k) {
+        const wv_step_item& it = items[k];
+        if (!it.d_q || !it.d_state || !it.d_scratch || it.nplanes < 1)
+            return fail(WV_EINVAL, "item %d: bad buffers", k);
+        std::vector<Sub> lay;
+        int rc = layout(m->cfg, it.H, it.W, lay);
+        if (rc) return rc;
+        const int i = it.subband, g = it.step;
+        if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3)
+            return fail(WV_EORDER, "item %d: subband %d / step %d out of range", k, i, g);
+        const Sub& S = lay[i];
+        const long long ng = wv_group_count(S.h, S.w, g);
+        if (ng > 0 && !it.d_params) return fail(WV_EINVAL, "item %d: null params", k);
+        const long long HW = (long long)it.H * it.W;
+        const size_t SS = state_floats(m->cfg, it.nplanes, it.H, it.W);
+        float* hcur = it.d_state + (size_t)(i & 1) * 2 * SS;
+        const long long st_ps = (long long)S.h * S.w * C;
+        const Scratch sc = scratch_layout(m->cfg, it.nplanes, it.H, it.W);
+        float* act[2] = {(float*)it.d_scratch + sc.act0, (float*)it.d_scratch + sc.act1};
+        ConvArgs base{};
+        base.N = it.nplanes;
+        base.h = S.h;
+        base.w = S.w;
+        base.tiles_x = (S.w + tw - 1) / tw;
+        base.tiles_y = (S.h + th - 1) / th;
+        if (g == 0) {
+            ConvArgs a = base;
+            a.sym_step = 4;
+            a.h_out = hcur;
+            a.c_out = hcur + SS;
+            a.st_ps = st_ps;
+            a.C = C;
+            if (i > 0) {
+                const Sub& Pv = lay[i - 1];
+                const int up = (S.h == 2 * Pv.h) ? 1 : 0;
+                float* hold = it.d_state + (size_t)((i - 1) & 1) * 2 * SS;
+                a.in = hold;
+                a.in_ps = (long long)Pv.h * Pv.w * C;
+                a.in_up = up;
+                a.sym = it.d_q + Pv.off;
+                a.sym_ps = HW;
+                a.sym_up = up;
+                a.c_prev = hold + SS;
+                a.cprev_ps = (long long)Pv.h * Pv.w * C;
+                a.cprev_up = up;
+            }
+            if (bf16) {
+                a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+                a.in = nullptr;
+                a.h16_out = reinterpret_cast<uint16_t*>(hcur);
+                a.h_out = nullptr;
+            }
+            item_seg(launches[0], bf16, bf16 ? nullptr : &m->lstm, bf16 ? &m->lstm16 : nullptr, a);
+        }
+        if (ng == 0) continue;
+        for (int l = 0; l < Lc; ++l) {
+            const bool last = l == Lc - 1;
+            ConvArgs a = base;
+            a.in = l == 0 ? hcur : act[(l - 1) & 1];
+            a.in_ps = st_ps;
+            if (l == 0 && g > 0) {
+                a.sym = it.d_q + S.off;
+                a.sym_ps = HW;
+                a.sym_step = g;
+            }
+            if (!last) {
+                a.out = act[l & 1];
+                a.out_ps = st_ps;
+                a.out_cs = C;
+            } else {
+                a.params = it.d_params;
+                a.step = g;
+                a.K = m->cfg.mix_k;
+                a.sigma_min = m->cfg.sigma_min;
+            }
+            if (bf16) {
+                a.in16 = reinterpret_cast<const uint16_t*>(a.in);
+                a.in = nullptr;
+                a.out16 = reinterpret_cast<uint16_t*>(a.out);
+                a.out = nullptr;
+            }
+            const int role = l == 0 ? (g > 0 ? 2 : 1) : (last ? (int)launches.size() - 1 : 2 + l);
+            item_seg(launches[role], bf16, bf16 ? nullptr : &m->ctx[S.type][g][l],
+                     bf16 ? &m->ctx16[S.type][g][l] : nullptr, a);
+        }
+    }
+    size_t total = 0;
+    for (auto& Lx : launches) {
+        item_finish(Lx, bf16);
+        total += (Lx.segs.size() + 255) & ~(size_t)255;
+    }
+    if (used_bytes) *used_bytes = total;
+    if (total == 0) return WV_OK;
+    if (!h_staging || !d_desc) return fail(WV_EINVAL, "null staging or descriptor buffer");
+    if (total > staging_bytes || total > desc_bytes)
+        return fail(WV_ENOMEM, "descriptors need %zu bytes", total);
+    size_t off = 0;
+    std::vector<size_t> offs;
+    for (auto& Lx : launches) {
+        offs.push_back(off);
+        memcpy((char*)h_staging + off, Lx.segs.data(), Lx.segs.size());
+        off += (Lx.segs.size() + 255) & ~(size_t)255;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(d_desc, h_staging, total, hipMemcpyHostToDevice, s));
+    for (size_t r = 0; r < launches.size(); ++r) {
+        const ItemLaunch& Lx = launches[r];
+        if (!Lx.nseg || !Lx.total) continue;
+        const int grid = (int)(Lx.total < 1024 ? Lx.total : 1024);
+        if (bf16)
+            HIPCHK(launch_conv_seg_bf16(reinterpret_cast<const ConvSeg16*>((char*)d_desc + offs[r]), Lx.nseg,
+                                        Lx.total, Lx.proto16, Lx.mode, Lx.nb, grid, s));
+        else
+            HIPCHK(launch_conv_seg(reinterpret_cast<const ConvSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
+                                   Lx.proto, Lx.mode, Lx.nb, grid, s));
     }
     return WV_OK;
 }

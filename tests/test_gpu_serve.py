@@ -1,0 +1,60 @@
+"""Continuous-batching server: each result is the same alone and in the mix (needs an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes, video_gop_420
+from gpu_common import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _alone(model, prep):
+    """Decode one prepared input by itself with the single-request calls."""
+    from paper_2405_12631_amd import codec
+    outs = []
+    for H, W, N, q_known, syms in prep.groups:
+        ws = codec.Workspace(model, N, H, W)
+        q = torch.zeros_like(q_known)
+        for i in range(len(ws.lay)):
+            for g in range(4):
+                prm = codec.context_params(model, q, ws, i, g)
+                codec.cdf_tables(model, prm, out=ws.cdf)
+                codec.scatter_symbols(model, syms[i][g], q, ws, i, g)
+        x, _ = codec.synthesize(model, ws, q=q, offset=128.0 if prep.kind == "image" else 0.0)
+        if prep.kind == "gop":
+            v = x.view(prep.T, -1)
+            codec.temporal_haar(v, inverse=True)
+            codec.add_offset(v, 128.0)
+        outs.append(x)
+    torch.cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_served_results_equal_alone_results(prec):
+    need_gpu()
+    from paper_2405_12631_amd import codec, serve, WV_BF16, WV_FP32
+    say("serve mix", prec)
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)),
+                        precision=WV_BF16 if prec == "bf16" else WV_FP32)
+    luma, chroma = video_gop_420(T=8, H=64, W=64, seed=5)
+    preps = {0: serve.Prepared(model, "image", sinusoid_1f_planes(64, 96, 3, seed=1)),
+             1: serve.Prepared(model, "image", sinusoid_1f_planes(32, 48, 3, seed=2)),
+             2: serve.Prepared(model, "gop", (luma, chroma))}
+    # Staggered arrivals: later requests join while earlier ones are mid-decode.
+    reqs = [(0.0, 0), (0.0, 2), (0.004, 1), (0.008, 0), (0.012, 2), (0.02, 1)]
+    budget = 3 * max(serve.footprint(model, p) for p in preps.values())     # forces queueing
+    srv = serve.Server(model, budget)
+    stats, done = srv.run(reqs, preps, max_seconds=60)
+    say(stats)
+    assert stats["completed"] == len(reqs) and stats["rejected"] == 0
+    alone = {pid: _alone(model, p) for pid, p in preps.items()}
+    for s in done:
+        for b, x in enumerate(s.xhat):
+            assert torch.equal(x, alone[s.req["prep"]][b]), (s.req, b)
+    # The GOP decodes back to frames close to the input (lossy, step 4).
+    g = [s for s in done if s.req["prep"] == 2][0]
+    err = (g.xhat[0].cpu().numpy() - luma.astype(np.float32)).std()
+    assert err < 8.0, err
