@@ -8,11 +8,12 @@ host entropy coder would return are taken from a device buffer), then
 dequantisation and synthesis.  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--precision fp32|bf16] [--workload ycbcr512x768|batch64_mixed]
+                    [--precision fp32|bf16] [--workload ycbcr512x768|batch64_mixed|serve_mix]
 
 The default is the FP32 batch-1 512x768 workload.  --workload batch64_mixed
 times a mixed-size batch of 64 images (BF16 context, persistent launches,
-graph replay, autotuned blocking).
+graph replay, autotuned blocking); --workload serve_mix runs the
+continuous-batching server under Poisson arrivals of stills and GOPs.
 
 Prints one JSON line.
 """
@@ -145,6 +146,71 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def bench_serve(args):
+    """Serving mix: Poisson arrivals (seed 4), 70% stills of the four batch sizes, 30% GOPs
+    of 8 frames 1088x1920 4:2:0 (temporal Haar, then the spatial codec per temporal
+    subband), BF16 context convs, admission by HBM footprint, continuous batching.
+    Each request refers to one of a few prepared inputs (symbols on the device, the
+    coder elided).  Runs the offered rate and a lower rate; value = sustained Mpixel/s
+    (luma pixels x frames for GOPs) under the offered rate."""
+    import torch
+    from paper_2405_12631_amd import codec, serve, WV_BF16, WV_FP32
+    from wvgen import get_config, make_weights, pack_weights, poisson_arrivals, sinusoid_1f_planes, \
+        video_gop_420
+
+    cfg = get_config("serve_mix")
+    prec = WV_FP32 if args.precision == "fp32" else WV_BF16
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=prec)
+    log = (lambda m: print(m, file=sys.stderr, flush=True))
+    preps, by_size = {}, {}
+    for k, hw in enumerate(cfg["sizes"]):
+        ids = []
+        for r in range(2):
+            pid = len(preps)
+            preps[pid] = serve.Prepared(model, "image", sinusoid_1f_planes(hw[0], hw[1], 3, seed=100 + 2 * k + r))
+            ids.append(pid)
+        by_size[tuple(hw)] = ids
+    gops = []
+    for r in range(2):
+        luma, chroma = video_gop_420(T=cfg["gop"], H=cfg["video_hw"][0], W=cfg["video_hw"][1],
+                                     seed=5 + r, shift_px=cfg["shift_px"])
+        pid = len(preps)
+        preps[pid] = serve.Prepared(model, "gop", (luma, chroma))
+        gops.append(pid)
+    torch.cuda.synchronize()
+    budget = int(args.serve_budget_gb * (1 << 30))
+    runs = {}
+    for rate in (cfg["rate_hz"], args.serve_low_rate):
+        arr = poisson_arrivals(rate, args.serve_seconds, cfg["frac_video"], cfg["sizes"],
+                               seed=cfg["seed_arrivals"])
+        reqs = []
+        for n, a in enumerate(arr):
+            pid = gops[n % 2] if a["kind"] == "gop" else by_size[a["size"]][n % 2]
+            reqs.append((a["t"], pid))
+        offered = sum(preps[p].pixels for _, p in reqs) / args.serve_seconds / 1e6
+        srv = serve.Server(model, budget)
+        stats, _ = srv.run(reqs, preps, admit_until=args.serve_seconds,
+                           max_seconds=args.serve_seconds + args.serve_drain, log=log)
+        stats.update(rate_hz=rate, arrivals=len(reqs), offered_mpx_per_s=round(offered, 2))
+        runs[f"{rate:g}_req_s"] = stats
+        torch.cuda.empty_cache()
+    hi = runs[f"{cfg['rate_hz']:g}_req_s"]
+    out = dict(
+        metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
+        value=hi["mpx_per_s"], unit="Mpixel/s", n_gpus=1, steps=hi["iterations"], warmup=0,
+        ms_per_step=round(hi["wall_s"] * 1e3 / max(hi["iterations"], 1), 3), higher_is_better=True,
+        scaling="weak", vs_baseline=None,
+        dtype=f"{args.precision} context convs (fp32 accumulate), fp32 lifting/cdf", data="synthetic",
+        config=dict(workload=f"serve_mix: Poisson arrivals at {cfg['rate_hz']:g} req/s for "
+                             f"{args.serve_seconds:g} s (then at most {args.serve_drain:g} s to drain), "
+                             "70% stills of the four batch sizes, 30% 8-frame 1088x1920 4:2:0 GOPs, "
+                             f"HBM budget {args.serve_budget_gb:g} GiB, continuous batching, coder elided",
+                    budget_gib=args.serve_budget_gb),
+        p50_ms=hi["p50_ms"], p99_ms=hi["p99_ms"], runs=runs,
+    )
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +220,12 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
                     help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
                          "bf16 for the batched workload")
-    ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed"], default="ycbcr512x768")
+    ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix"],
+                    default="ycbcr512x768")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run")
+    ap.add_argument("--serve-drain", type=float, default=20.0, help="time allowed to drain after it")
+    ap.add_argument("--serve-low-rate", type=float, default=10.0, help="second, lower arrival rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=150.0, help="HBM admission budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path (run with --gpus 1)",
@@ -163,6 +234,9 @@ def main():
     if args.workload == "batch64_mixed":
         args.precision = args.precision or "bf16"
         return bench_batch(args)
+    if args.workload == "serve_mix":
+        args.precision = args.precision or "bf16"
+        return bench_serve(args)
     args.precision = args.precision or "fp32"
 
     import torch

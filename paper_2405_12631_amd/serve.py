@@ -116,6 +116,12 @@ class Slot:
         self.done_event = torch.cuda.Event()
         self.done_event.record(torch.cuda.current_stream())
 
+    def release(self, keep_output):
+        """Return the request's device memory once its work has completed."""
+        self.ws, self.q = [], []
+        if not keep_output:
+            self.xhat = []
+
 
 class Server:
     """FIFO admission by footprint, continuous batching, one coding step per iteration."""
@@ -143,8 +149,9 @@ class Server:
         self.staging_ev[k] = ev
         return [s for s in slots if s.after_params(self.model)]
 
-    def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None):
-        """requests: list of (arrival_s, prep_id) sorted by time.  Returns (stats, slots)."""
+    def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None, keep_outputs=False):
+        """requests: list of (arrival_s, prep_id) sorted by time.  Returns (stats, slots);
+        finished slots keep their reconstruction only if keep_outputs."""
         m = self.model
         pending = deque(requests)
         queue, active, finishing, done = deque(), [], [], []
@@ -183,6 +190,7 @@ class Server:
                     s.req["finished"] = time.perf_counter() - t0
                     finishing.remove(s)
                     used -= fp[s.req["prep"]]
+                    s.release(keep_outputs)
                     done.append(s)
             if not (pending or queue or active or finishing):
                 break

@@ -47,7 +47,7 @@ def test_served_results_equal_alone_results(prec):
     reqs = [(0.0, 0), (0.0, 2), (0.004, 1), (0.008, 0), (0.012, 2), (0.02, 1)]
     budget = 3 * max(serve.footprint(model, p) for p in preps.values())     # forces queueing
     srv = serve.Server(model, budget)
-    stats, done = srv.run(reqs, preps, max_seconds=60)
+    stats, done = srv.run(reqs, preps, max_seconds=60, keep_outputs=True)
     say(stats)
     assert stats["completed"] == len(reqs) and stats["rejected"] == 0
     alone = {pid: _alone(model, p) for pid, p in preps.items()}
