@@ -211,6 +211,52 @@ def bench_serve(args):
     print(json.dumps(out))
 
 
+def precision_report(args):
+    """The 512x768x3 image with BF16 context convs against the FP32 path and the FP64
+    oracle: parameter error on plane 0 (every subband and step, the oracle run on the
+    decoded symbols), bits per pixel of real GPU-encoded bitstreams, and the GPU encode ->
+    GPU decode round trip."""
+    import torch
+    import oracle as O
+    from paper_2405_12631_amd import codec, WV_BF16, WV_FP32
+    from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes
+
+    cfg = get_config("ycbcr512x768")
+    H, W, N = cfg["H"], cfg["W"], cfg["planes"]
+    w = make_weights(cfg)
+    blob = pack_weights(cfg, w)
+    x = sinusoid_1f_planes(H, W, planes=N, seed=cfg["seed_image"])
+    out = dict(workload="ycbcr512x768 precision report", H=H, W=W, planes=N)
+    qs_ref = None
+    for name, prec in (("fp32", WV_FP32), ("bf16", WV_BF16)):
+        model = codec.Model(cfg, blob, precision=prec)
+        data, q_enc = codec.encode(model, x)
+        _, _, q_dec = codec.decode(model, data)
+        torch.cuda.synchronize()
+        r = dict(bytes=len(data), bpp=round(len(data) * 8 / (H * W), 5),
+                 roundtrip_bit_exact=bool(torch.equal(q_enc, q_dec)))
+        if qs_ref is None:
+            qs_ref = O.unpack(q_enc.cpu().numpy().astype(np.int64)[:1], cfg, H, W)
+            t0 = time.perf_counter()
+            ref = O.context_params_all(qs_ref, cfg, w)
+            out["oracle_seconds_plane0"] = round(time.perf_counter() - t0, 2)
+        ws = codec.Workspace(model, 1, H, W)
+        got = codec.params_all(model, torch.from_numpy(O.pack(qs_ref).astype(np.int16)).cuda(), ws)
+        rel = []
+        for i in range(len(ref)):
+            for g in range(4):
+                a = got[i][g].cpu().numpy().astype(np.float64).reshape(-1, 9)
+                b = ref[i][g].reshape(-1, 9)
+                den = np.abs(b)
+                den[:, :6] = np.maximum(den[:, :6], 1e-2)
+                rel.append((np.abs(a - b) / den).ravel())
+        rel = np.concatenate(rel)
+        r.update(param_rel_err_max=float(rel.max()), param_rel_err_mean=float(rel.mean()))
+        out[name] = r
+    out["bpp_delta_bf16_vs_fp32"] = round(out["bf16"]["bpp"] - out["fp32"]["bpp"], 5)
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,7 +266,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
                     help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
                          "bf16 for the batched workload")
-    ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix"],
+    ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix",
+                                           "precision_report"],
                     default="ycbcr512x768")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=20.0, help="time allowed to drain after it")
@@ -234,6 +281,8 @@ def main():
     if args.workload == "batch64_mixed":
         args.precision = args.precision or "bf16"
         return bench_batch(args)
+    if args.workload == "precision_report":
+        return precision_report(args)
     if args.workload == "serve_mix":
         args.precision = args.precision or "bf16"
         return bench_serve(args)

@@ -344,3 +344,28 @@ def test_autoregressive_ll_model(name, H, W, N):
     q = torch.zeros_like(q_enc)
     with pytest.raises(L.WvError):
         codec.ar_decode(model, q, codec.Workspace(model, N, H, W), [bytes(ll)] + [s[0][0] for s in bad[1:]])
+
+
+def test_full_size_plane_parity_in_bench_configuration():
+    """512 x 768, the benchmark's model and launch configuration (three planes per call):
+    every parameter of plane 0 (all 13 subbands x 4 steps) and its reconstruction against
+    the oracle; the oracle runs on the GPU encoder's own symbols."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("full size 512x768")
+    cfg = get_config("ycbcr512x768")
+    model, w = model_for(cfg)
+    x = sinusoid_1f_planes(512, 768, planes=3, seed=cfg["seed_image"])
+    ws = codec.Workspace(model, 3, 512, 768)
+    q, _, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws)
+    got = codec.params_all(model, q, ws)
+    qs = O.unpack(q.cpu().numpy().astype(np.int64)[:1], cfg, 512, 768)
+    ref = O.context_params_all(qs, cfg, w)
+    worst = max(param_err(got[i][g][:1].cpu().numpy(), ref[i][g], 3) for i in range(13) for g in range(4))
+    say("full-size worst param rel err", worst)
+    assert worst <= PARAM_RTOL
+    cdf = codec.cdf_tables(model, got[12][3][:1].contiguous())
+    check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[12][3][:1].cpu().numpy(), cfg)
+    xh, _ = codec.synthesize(model, ws, q=q)
+    ref_x = O.synthesize(O.dequantize(qs, cfg), cfg, w)
+    assert np.max(np.abs(xh[:1].cpu().numpy() - ref_x)) <= XHAT_ATOL
