@@ -623,6 +623,11 @@ inline CView cvw(const float* p, long long ps, int rs, int cs) { return CView{p,
 // out = A + sign * (predict ? z + N(z) : z/2 + N(z)) on an h x w array.
 int run_filter(const wv_model* m, int f, CView z, CView A, View out, int N, int h, int w,
                int predict, float sign, float* a1, float* a2, hipStream_t s) {
+    if (m->lift_mid[f].size() == 1) {   // three layers: the fused kernel keeps them in LDS
+        HIPCHK(launch_lift_fused(m->lift_first[f], m->lift_mid[f][0], m->lift_last[f], z, A, out, N, h, w,
+                                 predict, sign, m->cfg.lift_int, s));
+        return WV_OK;
+    }
     HIPCHK(launch_lift_first(m->lift_first[f], z, N, h, w, a1, s));
     float* cur = a1;
     float* oth = a2;

@@ -153,6 +153,10 @@ hipError_t launch_ar_params(const ArModel& M, const int16_t* q, long long q_ps, 
                             float* params, hipStream_t s);
 hipError_t launch_ar_decode(const ArModel& M, const ArStreams& S, int16_t* q, long long q_ps, int h,
                             int w, int N, int smin, int nsym, int* status, hipStream_t s);
+// A whole three-layer predict/update filter and its lifting update in one kernel.
+hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A,
+                             View out, int N, int h, int w, int predict, float sign, int lift_int,
+                             hipStream_t s);
 hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s);
 hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
                            float dL, float dH, int smin, int smax, int* clip, hipStream_t s);

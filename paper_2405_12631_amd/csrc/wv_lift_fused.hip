@@ -1,0 +1,192 @@
+// One predict/update filter application in a single kernel (Sec. 3.1):
+//   out = A + sign * f,  f = z + N(z) (predict) or z/2 + N(z) (update),
+//   N = conv3x3(C -> 1) . tanh . conv3x3(C -> C) . tanh . conv3x3(1 -> C),
+// every conv zero-padded at the array border.  A workgroup owns an 8 x 16
+// output tile and keeps the whole chain in LDS: z on a 14 x 22 halo, the
+// first layer on 12 x 20 positions (vector ALUs), the second on 10 x 18
+// positions as an implicit GEMM on v_mfma_f32_16x16x4f32 (its output then
+// overwrites the first layer's buffer), the last layer and the update on the
+// 8 x 16 outputs.  Positions outside the array are zero in every layer, which
+// is exactly the per-layer zero padding of the definition.
+#include "wv_internal.h"
+
+namespace wv {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int OH = 8, OW = 16;
+constexpr int ZH = OH + 6, ZW = OW + 6;   // z halo
+constexpr int AH = OH + 4, AW = OW + 4;   // first layer region
+constexpr int BH = OH + 2, BW = OW + 2;   // second layer region
+
+template <int C>
+__global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const MfmaLayer L2, const VecLayer L3,
+                                                   const CView z, const CView A, const View out, int N,
+                                                   int h, int w, int tiles_x, int tiles_y, int predict,
+                                                   float sign, int lift_int) {
+    constexpr int S1 = C + 4;               // floats per position in the layer buffers
+    constexpr int NP2 = BH * BW;            // 180 second-layer positions
+    constexpr int MB2 = (NP2 + 15) / 16;    // 12 M blocks
+    constexpr int CB = C / 16;              // K chunks (16 channels) per tap
+    constexpr int NBT = C / 16;             // output blocks of 16
+    constexpr int MBW = (MB2 + 3) / 4;      // M blocks per wave (3)
+    __shared__ float zs[ZH * ZW];
+    __shared__ __attribute__((aligned(16))) float act[AH * AW * S1];   // layer 1, then layer 2
+    __shared__ __attribute__((aligned(16))) float4 w2s[9 * CB * NBT * 64];
+    __shared__ float w1s[9 * C], b1s[C], w3s[9 * C], b2s[C];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int t = blockIdx.x;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int ty = t % tiles_y;
+    const int n = t / tiles_y;
+    const int r0 = ty * OH, c0 = tx * OW;
+
+    // weights and the z halo
+    for (int i = tid; i < 9 * CB * NBT * 64; i += 256) w2s[i] = reinterpret_cast<const float4*>(L2.w)[i];
+    for (int i = tid; i < 9 * C; i += 256) {
+        w1s[i] = L1.w[i];
+        w3s[i] = L3.w[i];
+    }
+    for (int i = tid; i < C; i += 256) {
+        b1s[i] = L1.bias[i];
+        b2s[i] = L2.bias[i];
+    }
+    const float* zp = z.p + (long long)n * z.ps;
+    for (int i = tid; i < ZH * ZW; i += 256) {
+        const int r = r0 - 3 + i / ZW, c = c0 - 3 + i % ZW;
+        zs[i] = (r >= 0 && r < h && c >= 0 && c < w) ? zp[(long long)r * z.rs + (long long)c * z.cs] : 0.f;
+    }
+    __syncthreads();
+
+    // layer 1 on the 12 x 20 region: tanh(b1 + sum_tap w1 z), zero outside the array
+    for (int i = tid; i < AH * AW * (C / 4); i += 256) {
+        const int pos = i / (C / 4);
+        const int c4 = (i - pos * (C / 4)) * 4;
+        const int ay = pos / AW, ax = pos % AW;
+        const int r = r0 - 2 + ay, c = c0 - 2 + ax;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r >= 0 && r < h && c >= 0 && c < w) {
+            float zv[9];
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) zv[tap] = zs[(ay + tap / 3) * ZW + ax + tap % 3];
+            float s[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                s[j] = b1s[c4 + j];
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) s[j] = fmaf(w1s[tap * C + c4 + j], zv[tap], s[j]);
+            }
+            v = make_float4(tanhf(s[0]), tanhf(s[1]), tanhf(s[2]), tanhf(s[3]));
+        }
+        *reinterpret_cast<float4*>(act + pos * S1 + c4) = v;
+    }
+    __syncthreads();
+
+    // layer 2 on the 10 x 18 region: MFMA over K = 9 taps x C channels
+    const int m = lane & 15;
+    const int kk = lane >> 4;
+    floatx4 acc[MBW][NBT];
+    int apos[MBW];
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) {
+        const int mb = wave * MBW + j;
+        int p = mb * 16 + m;
+        p = p < NP2 ? p : NP2 - 1;                          // dummy rows read a valid position
+        apos[j] = (p / BW) * AW + (p % BW);
+#pragma unroll
+        for (int nb = 0; nb < NBT; ++nb) acc[j][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int tap = 0; tap < 9; ++tap) {
+        const int toff = (tap / 3) * AW + tap % 3;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            float4 bv[NBT];
+#pragma unroll
+            for (int nb = 0; nb < NBT; ++nb) bv[nb] = w2s[((tap * CB + cb) * NBT + nb) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < MBW; ++j) {
+                if (wave * MBW + j >= MB2) continue;
+                const float4 av =
+                    *reinterpret_cast<const float4*>(act + (apos[j] + toff) * S1 + cb * 16 + kk * 4);
+#pragma unroll
+                for (int nb = 0; nb < NBT; ++nb) {
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[nb].x, acc[j][nb], 0, 0, 0);
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[nb].y, acc[j][nb], 0, 0, 0);
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[nb].z, acc[j][nb], 0, 0, 0);
+                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[nb].w, acc[j][nb], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();   // layer 1 is dead; its buffer takes layer 2
+    const int col = lane & 15;
+    const int rowq = (lane >> 4) * 4;
+#pragma unroll
+    for (int j = 0; j < MBW; ++j) {
+        const int mb = wave * MBW + j;
+        if (mb >= MB2) continue;
+#pragma unroll
+        for (int nb = 0; nb < NBT; ++nb) {
+            const int ch = nb * 16 + col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = mb * 16 + rowq + i;
+                if (p >= NP2) continue;
+                const int r = r0 - 1 + p / BW, c = c0 - 1 + p % BW;
+                const bool in = r >= 0 && r < h && c >= 0 && c < w;
+                act[p * S1 + ch] = in ? tanhf(acc[j][nb][i] + b2s[ch]) : 0.f;
+            }
+        }
+    }
+    __syncthreads();
+
+    // layer 3 and the lifting update: two threads per output, halves of the channels
+    {
+        const int o = tid >> 1;
+        const int half = tid & 1;
+        const int oy = o / OW, ox = o % OW;
+        float s = 0.f;
+        for (int tap = 0; tap < 9; ++tap) {
+            const float* ap = act + ((oy + tap / 3) * BW + ox + tap % 3) * S1 + half * (C / 2);
+            const float* wp = w3s + tap * C + half * (C / 2);
+#pragma unroll
+            for (int k = 0; k < C / 2; ++k) s = fmaf(wp[k], ap[k], s);
+        }
+        const float other = __shfl_xor(s, 1);
+        const int r = r0 + oy, c = c0 + ox;
+        if (half == 0 && r < h && c < w) {
+            const float v = L3.bias[0] + (s + other);
+            const float zz = zs[(oy + 3) * ZW + ox + 3];
+            float f = predict ? zz + v : 0.5f * zz + v;
+            if (lift_int) f = rintf(f);
+            const float av = A.p[(long long)n * A.ps + (long long)r * A.rs + (long long)c * A.cs];
+            out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = av + sign * f;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A,
+                             View out, int N, int h, int w, int predict, float sign, int lift_int,
+                             hipStream_t s) {
+    if ((long long)N * h * w == 0) return hipSuccess;
+    const int tx = (w + OW - 1) / OW, ty = (h + OH - 1) / OH;
+    const dim3 grid((unsigned)(tx * ty * N));
+    if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2)
+        hipLaunchKernelGGL(lift_fused_k<32>, grid, dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx, ty,
+                           predict, sign, lift_int);
+    else if (L1.ch == 16 && L2.cin == 16 && L2.nbt == 1)
+        hipLaunchKernelGGL(lift_fused_k<16>, grid, dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx, ty,
+                           predict, sign, lift_int);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace wv
