@@ -48,6 +48,38 @@ def context_flops_per_coef(cfg):
     return 2.0 * (lstm + stacks)
 
 
+def lifting_cost_per_px(cfg):
+    """Algorithmic FLOPs and HBM bytes of synthesis per pixel of one plane.
+
+    Each predict/update application costs 9 (C^2 + 2 C) MACs per position and
+    reads its filter input and the array it updates and writes the result
+    (12 bytes).  Level j runs 2 (H/2^(j-1)) (W/2^(j-1)) applications: four over
+    the quarter-size column pairs, two over the half-size row arrays.  Add the
+    dequantisation (2 B in, 4 B out) and the final 8-bit rounding (4 B in, 1 B out).
+    """
+    C, J = cfg["lift_ch"], cfg["levels"]
+    apps = 2.0 * sum(4.0 ** -j for j in range(J))
+    return apps * 2.0 * 9 * (C * C + 2 * C), apps * 12.0 + 6.0 + 5.0
+
+
+def cdf_bytes_per_row(cfg):
+    """Algorithmic HBM bytes per CDF row: 3K float parameters in, one uint16 table out."""
+    return 12.0 * cfg["mix_k"] + 2.0 * (cfg["sym_max"] - cfg["sym_min"] + 2)
+
+
+def stage_rates(cfg, rows, px, cdf_ms, syn_ms):
+    """Achieved algorithmic rates of the CDF and synthesis stages of one decode
+    (CDF: one row per coefficient; synthesis: every pixel of every plane)."""
+    cb = cdf_bytes_per_row(cfg) * rows
+    lf, lb = lifting_cost_per_px(cfg)
+    out = dict(cdf=dict(bound="hbm", bytes=cb, gb_per_s=round(cb / cdf_ms / 1e6, 1),
+                        frac_hbm=round(cb / cdf_ms / 1e6 / HBM_PEAK_GBS, 4)),
+               synthesis=dict(bound="mfma", flops=lf * px, tflop_per_s=round(lf * px / syn_ms / 1e9, 3),
+                              frac_fp32_mfma=round(lf * px / syn_ms / 1e9 / MFMA_PEAK_TFLOPS["fp32"], 4),
+                              bytes=lb * px, gb_per_s=round(lb * px / syn_ms / 1e6, 1)))
+    return out
+
+
 def cpu_baseline(cfg, w, x, q_planes):
     """The FP64 oracle's decode path on plane 0 only (a third of one image)."""
     import oracle as O
@@ -319,6 +351,9 @@ def main():
                     ev[1].append(torch.cuda.Event(enable_timing=True))
                     ev[1][-1].record(stream)
                 codec.cdf_tables(model, prm, out=ws.cdf)
+                if ev is not None:
+                    ev[4].append(torch.cuda.Event(enable_timing=True))
+                    ev[4][-1].record(stream)
                 codec.scatter_symbols(model, syms[i][g], q, ws, i, g)
         if ev is not None:
             ev[2].append(torch.cuda.Event(enable_timing=True))
@@ -333,7 +368,7 @@ def main():
     torch.cuda.synchronize()
     assert torch.equal(q, q_known), "decode did not reproduce the symbols"
 
-    ev = ([], [], [], [])
+    ev = ([], [], [], [], [])
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -348,6 +383,7 @@ def main():
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     ctx_ms = np.array([a.elapsed_time(b) for a, b in zip(ev[0], ev[1])]).reshape(args.steps, -1)
     syn_ms = np.array([a.elapsed_time(b) for a, b in zip(ev[2], ev[3])])
+    cdf_ms = np.array([a.elapsed_time(b) for a, b in zip(ev[1], ev[4])]).reshape(args.steps, -1)
     ms_step = elapsed * 1e3 / args.steps
     mpx = H * W * args.steps / elapsed / 1e6
 
@@ -376,9 +412,12 @@ def main():
                     batch=1, planes=N, H=H, W=W),
         p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
         stage_ms=dict(context=round(float(ctx_ms.sum(1).mean()), 3),
+                      cdf=round(float(cdf_ms.sum(1).mean()), 3),
                       synthesis=round(float(syn_ms.mean()), 3),
-                      cdf_scatter_rest=round(float(lat.mean() - ctx_ms.sum(1).mean() - syn_ms.mean()), 3)),
+                      scatter_rest=round(float(lat.mean() - ctx_ms.sum(1).mean() - cdf_ms.sum(1).mean()
+                                               - syn_ms.mean()), 3)),
         roofline=roof,
+        stage_rates=stage_rates(cfg, N * H * W, N * H * W, float(cdf_ms.sum(1).mean()), float(syn_ms.mean())),
     )
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, w, x, q_known.cpu().numpy().astype(np.int64))

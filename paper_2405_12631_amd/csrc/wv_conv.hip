@@ -100,20 +100,29 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
     {
         const int win = a.w >> a.in_up;
         const float* inp = a.in ? a.in + (long long)n * a.in_ps : nullptr;
-        for (int idx = tid; idx < HALO * (CIN / 4); idx += 256) {
-            const int pos = idx / (CIN / 4);
-            const int c4 = idx - pos * (CIN / 4);
+        constexpr int V = CIN / 4;                   // float4 per position
+        constexpr int NH = (HALO * V + 255) / 256;   // per thread: all loads in flight before any store
+        float4 hv[NH];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const int idx = tid + k * 256;
+            const int pos = idx / V;
+            const int c4 = idx - pos * V;
             const int hy = pos / HALO_W;
-            const int hx = pos - hy * HALO_W;
             const int r = r0 + hy - 1;
-            const int c = c0 + hx - 1;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (inp && r >= 0 && r < a.h && c >= 0 && c < a.w) {
-                const long long off =
-                    ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c4 * 4;
-                v = *reinterpret_cast<const float4*>(inp + off);
+            const int c = c0 + (pos - hy * HALO_W) - 1;
+            hv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (idx < HALO * V && inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
+                hv[k] = *reinterpret_cast<const float4*>(
+                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c4 * 4);
+        }
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const int idx = tid + k * 256;
+            if (idx < HALO * V) {
+                const int pos = idx / V;
+                *reinterpret_cast<float4*>(lds_in + pos * STRIDE + (idx - pos * V) * 4) = hv[k];
             }
-            *reinterpret_cast<float4*>(lds_in + pos * STRIDE + c4 * 4) = v;
         }
         if (SYM) {
             const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
@@ -306,7 +315,7 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
 }
 
 template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
     conv_tile_f32<CIN, NB, SYM, MODE, TAPS>(L, a, blockIdx.x, blockIdx.y);
 }
 
@@ -315,7 +324,7 @@ __global__ __launch_bounds__(256) void conv3x3_mfma_f32(const MfmaLayer L, const
 // Segment s covers items [item0, item0 + tiles * columns); its item i is tile
 // i % tiles of column i / tiles.  Static assignment: no atomics, same bits.
 template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__global__ __launch_bounds__(256) void conv3x3_mfma_f32_seg(const ConvSeg* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_f32_seg(const ConvSeg* __restrict__ segs, int nseg,
                                                     long long total) {
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         int lo = 0, hi = nseg;

@@ -93,19 +93,29 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     {
         const int win = a.w >> a.in_up;
         const uint16_t* inp = a.in16 ? a.in16 + (long long)n * a.in_ps : nullptr;
-        constexpr int V = CIN / 8;   // uint4 per position
-        for (int idx = tid; idx < HALO * V; idx += 256) {
+        constexpr int V = CIN / 8;                   // uint4 per position
+        constexpr int NH = (HALO * V + 255) / 256;   // per thread: all loads in flight before any store
+        uint4 hv[NH];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const int idx = tid + k * 256;
             const int pos = idx / V;
             const int c8 = idx - pos * V;
             const int hy = pos / HWD;
-            const int hx = pos - hy * HWD;
             const int r = r0 + hy - 1;
-            const int c = c0 + hx - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
-                v = *reinterpret_cast<const uint4*>(
+            const int c = c0 + (pos - hy * HWD) - 1;
+            hv[k] = make_uint4(0, 0, 0, 0);
+            if (idx < HALO * V && inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
+                hv[k] = *reinterpret_cast<const uint4*>(
                     inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c8 * 8);
-            *reinterpret_cast<uint4*>(lds_in + pos * STRIDE + c8 * 8) = v;
+        }
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const int idx = tid + k * 256;
+            if (idx < HALO * V) {
+                const int pos = idx / V;
+                *reinterpret_cast<uint4*>(lds_in + pos * STRIDE + (idx - pos * V) * 8) = hv[k];
+            }
         }
         if (SYM) {
             const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
@@ -140,33 +150,47 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     // tile row of accumulator block mb
     auto row_of = [&](int mb) { return MODE == CONV_HEAD ? wave * 4 + 2 * mb + gr : wave * 4 + mb; };
 
+    // Steps (tap, 32-channel chunk) run in order; the A fragments of the next step
+    // are read while this step's MFMAs run (the halo is not written in the loop,
+    // so only the B slices need the per-tap barrier).  Fully unrolled so that the
+    // fragment double buffer stays in registers.
+    uint4 afr[2][MB];
+#define WV_LOAD_A(dst, tp, ccv)                                                                      \
+    _Pragma("unroll") for (int mb_ = 0; mb_ < MB; ++mb_) dst[mb_] = *reinterpret_cast<const uint4*>( \
+        lds_in + ((row_of(mb_) + (tp) / 3) * HWD + m + (tp) % 3) * STRIDE + (ccv) * 32 + kk * 8);
+    WV_LOAD_A(afr[0], 0, 0)
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int buf = tap & 1;
         if (tap < 8) {
             WV_LOAD_B(tap + 1)
         }
-        const int dy = tap / 3;
-        const int dx = tap - dy * 3;
+        uint4 bv[CC][NB];
+#pragma unroll
+        for (int cc = 0; cc < CC; ++cc)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bv[cc][nb] = lds_w[buf][(cc * NB + nb) * 64 + lane];
 #pragma unroll
         for (int cc = 0; cc < CC; ++cc) {
-            uint4 bv[NB];
+            const int st = tap * CC + cc;
+            if (cc + 1 < CC) {
+                WV_LOAD_A(afr[(st + 1) & 1], tap, cc + 1)
+            } else if (tap < 8) {
+                WV_LOAD_A(afr[(st + 1) & 1], tap + 1, 0)
+            }
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) bv[nb] = lds_w[buf][(cc * NB + nb) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const uint4 av = *reinterpret_cast<const uint4*>(
-                    lds_in + ((row_of(mb) + dy) * HWD + m + dx) * STRIDE + cc * 32 + kk * 8);
+            for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(av), as_bf(bv[nb]),
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(afr[st & 1][mb]), as_bf(bv[cc][nb]),
                                                                           acc[mb][nb], 0, 0, 0);
-            }
         }
         if (tap < 8) {
             WV_STORE_B(buf ^ 1)   // the other buffer was last read one tap ago
             __syncthreads();
         }
     }
+#undef WV_LOAD_A
 #undef WV_LOAD_B
 #undef WV_STORE_B
     if (SYM) {
@@ -276,13 +300,13 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 }
 
 template <int CIN, int NB, bool SYM, int MODE>
-__global__ __launch_bounds__(256) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
     conv_tile_bf16<CIN, NB, SYM, MODE>(L, a, blockIdx.x, blockIdx.y);
 }
 
 // Persistent multi-segment form (see the FP32 kernel).
 template <int CIN, int NB, bool SYM, int MODE>
-__global__ __launch_bounds__(256) void conv3x3_mfma_bf16_seg(const ConvSeg16* __restrict__ segs, int nseg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16_seg(const ConvSeg16* __restrict__ segs, int nseg,
                                                      long long total) {
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         int lo = 0, hi = nseg;

@@ -34,7 +34,8 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     __shared__ float zs[ZH * ZW];
     __shared__ __attribute__((aligned(16))) float act[AH * AW * S1];   // layer 1, then layer 2
     __shared__ __attribute__((aligned(16))) float4 w2s[9 * CB * NBT * 64];
-    __shared__ float w1s[9 * C], b1s[C], w3s[9 * C], b2s[C];
+    __shared__ float w1s[9 * C], b1s[C], b2s[C];
+    __shared__ __attribute__((aligned(16))) float w3s[9 * C];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -46,8 +47,23 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     const int n = t / tiles_y;
     const int r0 = ty * OH, c0 = tx * OW;
 
-    // weights and the z halo
-    for (int i = tid; i < 9 * CB * NBT * 64; i += 256) w2s[i] = reinterpret_cast<const float4*>(L2.w)[i];
+    static_assert(MBW * 4 == MB2, "the four waves split the M blocks evenly");
+    // weights and the z halo; every thread's loads are in flight before its first store
+    {
+        constexpr int NW = (9 * CB * NBT * 64 + 255) / 256;
+        float4 wv[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int i = tid + k * 256;
+            wv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (i < 9 * CB * NBT * 64) wv[k] = reinterpret_cast<const float4*>(L2.w)[i];
+        }
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int i = tid + k * 256;
+            if (i < 9 * CB * NBT * 64) w2s[i] = wv[k];
+        }
+    }
     for (int i = tid; i < 9 * C; i += 256) {
         w1s[i] = L1.w[i];
         w3s[i] = L3.w[i];
@@ -101,35 +117,41 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
 #pragma unroll
         for (int nb = 0; nb < NBT; ++nb) acc[j][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    for (int tap = 0; tap < 9; ++tap) {
-        const int toff = (tap / 3) * AW + tap % 3;
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            float4 bv[NBT];
-#pragma unroll
-            for (int nb = 0; nb < NBT; ++nb) bv[nb] = w2s[((tap * CB + cb) * NBT + nb) * 64 + lane];
-#pragma unroll
-            for (int j = 0; j < MBW; ++j) {
-                if (wave * MBW + j >= MB2) continue;
-                const float4 av =
-                    *reinterpret_cast<const float4*>(act + (apos[j] + toff) * S1 + cb * 16 + kk * 4);
-#pragma unroll
-                for (int nb = 0; nb < NBT; ++nb) {
-                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv[nb].x, acc[j][nb], 0, 0, 0);
-                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv[nb].y, acc[j][nb], 0, 0, 0);
-                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv[nb].z, acc[j][nb], 0, 0, 0);
-                    acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv[nb].w, acc[j][nb], 0, 0, 0);
-                }
-            }
-        }
+    // (tap, 16-channel chunk) steps in order; the fragments of the next step are
+    // read while this step's MFMAs run (fully unrolled: the double buffer stays
+    // in registers).
+    float4 afr[2][MBW], bfr[2][NBT];
+#define WV_LOAD_F(buf, tp, cbv)                                                                     \
+    {                                                                                               \
+        _Pragma("unroll") for (int nb_ = 0; nb_ < NBT; ++nb_) bfr[buf][nb_] =                       \
+            w2s[(((tp) * CB + (cbv)) * NBT + nb_) * 64 + lane];                                     \
+        _Pragma("unroll") for (int j_ = 0; j_ < MBW; ++j_) afr[buf][j_] = *reinterpret_cast<const float4*>( \
+            act + (apos[j_] + ((tp) / 3) * AW + (tp) % 3) * S1 + (cbv) * 16 + kk * 4);              \
     }
+#define WV_STEP(cur, st)                                                                            \
+    {                                                                                               \
+        if ((st) + 1 < 9 * CB) WV_LOAD_F((cur) ^ 1, ((st) + 1) / CB, ((st) + 1) % CB)                 \
+        _Pragma("unroll") for (int j = 0; j < MBW; ++j) _Pragma("unroll") for (int nb = 0; nb < NBT; ++nb) { \
+            acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].x, bfr[cur][nb].x, acc[j][nb], 0, 0, 0); \
+            acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].y, bfr[cur][nb].y, acc[j][nb], 0, 0, 0); \
+            acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].z, bfr[cur][nb].z, acc[j][nb], 0, 0, 0); \
+            acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].w, bfr[cur][nb].w, acc[j][nb], 0, 0, 0); \
+        }                                                                                           \
+    }
+    WV_LOAD_F(0, 0, 0)
+    for (int st = 0; st + 1 < 9 * CB; st += 2) {   // pairs of steps: buffer 0, then buffer 1
+        WV_STEP(0, st)
+        WV_STEP(1, st + 1)
+    }
+    if ((9 * CB) & 1) WV_STEP(0, 9 * CB - 1)
+#undef WV_STEP
+#undef WV_LOAD_F
     __syncthreads();   // layer 1 is dead; its buffer takes layer 2
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
 #pragma unroll
     for (int j = 0; j < MBW; ++j) {
         const int mb = wave * MBW + j;
-        if (mb >= MB2) continue;
 #pragma unroll
         for (int nb = 0; nb < NBT; ++nb) {
             const int ch = nb * 16 + col;
@@ -151,11 +173,19 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
         const int half = tid & 1;
         const int oy = o / OW, ox = o % OW;
         float s = 0.f;
-        for (int tap = 0; tap < 9; ++tap) {
-            const float* ap = act + ((oy + tap / 3) * BW + ox + tap % 3) * S1 + half * (C / 2);
-            const float* wp = w3s + tap * C + half * (C / 2);
 #pragma unroll
-            for (int k = 0; k < C / 2; ++k) s = fmaf(wp[k], ap[k], s);
+        for (int tap = 0; tap < 9; ++tap) {
+            const float4* ap = reinterpret_cast<const float4*>(act + ((oy + tap / 3) * BW + ox + tap % 3) * S1 +
+                                                               half * (C / 2));
+            const float4* wp = reinterpret_cast<const float4*>(w3s + tap * C + half * (C / 2));
+#pragma unroll
+            for (int k = 0; k < C / 8; ++k) {
+                const float4 av = ap[k], wv = wp[k];
+                s = fmaf(wv.x, av.x, s);
+                s = fmaf(wv.y, av.y, s);
+                s = fmaf(wv.z, av.z, s);
+                s = fmaf(wv.w, av.w, s);
+            }
         }
         const float other = __shfl_xor(s, 1);
         const int r = r0 + oy, c = c0 + ox;
