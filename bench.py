@@ -28,7 +28,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
+
+
+def _precision(name):
+    from paper_2405_12631_amd import WV_BF16, WV_FP32, WV_FP8
+    return {"fp32": WV_FP32, "bf16": WV_BF16, "fp8": WV_FP8}[name]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -106,11 +111,11 @@ def bench_batch(args):
     per-level blocking autotuned before timing.  One step = one graph replay = one
     coder-elided decode of all 64 images."""
     import torch
-    from paper_2405_12631_amd import batch as B, codec, WV_BF16, WV_FP32
+    from paper_2405_12631_amd import batch as B, codec
     from wvgen import batch_sizes, get_config, make_weights, pack_weights, sinusoid_1f_planes
 
     cfg = get_config("batch64_mixed")
-    prec = WV_FP32 if args.precision == "fp32" else WV_BF16
+    prec = _precision(args.precision)
     model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=prec)
     sizes, seeds = batch_sizes(cfg["batch"], cfg["sizes"], seed=cfg["seed_image"])
     images = [sinusoid_1f_planes(h, w, planes=3, seed=sd) for (h, w), sd in zip(sizes, seeds)]
@@ -186,12 +191,12 @@ def bench_serve(args):
     coder elided).  Runs the offered rate and a lower rate; value = sustained Mpixel/s
     (luma pixels x frames for GOPs) under the offered rate."""
     import torch
-    from paper_2405_12631_amd import codec, serve, WV_BF16, WV_FP32
+    from paper_2405_12631_amd import codec, serve
     from wvgen import get_config, make_weights, pack_weights, poisson_arrivals, sinusoid_1f_planes, \
         video_gop_420
 
     cfg = get_config("serve_mix")
-    prec = WV_FP32 if args.precision == "fp32" else WV_BF16
+    prec = _precision(args.precision)
     model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=prec)
     log = (lambda m: print(m, file=sys.stderr, flush=True))
     preps, by_size = {}, {}
@@ -244,13 +249,13 @@ def bench_serve(args):
 
 
 def precision_report(args):
-    """The 512x768x3 image with BF16 context convs against the FP32 path and the FP64
+    """The 512x768x3 image with BF16 and FP8 context convs against the FP32 path and the FP64
     oracle: parameter error on plane 0 (every subband and step, the oracle run on the
     decoded symbols), bits per pixel of real GPU-encoded bitstreams, and the GPU encode ->
     GPU decode round trip."""
     import torch
     import oracle as O
-    from paper_2405_12631_amd import codec, WV_BF16, WV_FP32
+    from paper_2405_12631_amd import codec, WV_BF16, WV_FP32, WV_FP8
     from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes
 
     cfg = get_config("ycbcr512x768")
@@ -260,7 +265,7 @@ def precision_report(args):
     x = sinusoid_1f_planes(H, W, planes=N, seed=cfg["seed_image"])
     out = dict(workload="ycbcr512x768 precision report", H=H, W=W, planes=N)
     qs_ref = None
-    for name, prec in (("fp32", WV_FP32), ("bf16", WV_BF16)):
+    for name, prec in (("fp32", WV_FP32), ("bf16", WV_BF16), ("fp8", WV_FP8)):
         model = codec.Model(cfg, blob, precision=prec)
         data, q_enc = codec.encode(model, x)
         _, _, q_dec = codec.decode(model, data)
@@ -286,6 +291,7 @@ def precision_report(args):
         r.update(param_rel_err_max=float(rel.max()), param_rel_err_mean=float(rel.mean()))
         out[name] = r
     out["bpp_delta_bf16_vs_fp32"] = round(out["bf16"]["bpp"] - out["fp32"]["bpp"], 5)
+    out["bpp_delta_fp8_vs_fp32"] = round(out["fp8"]["bpp"] - out["fp32"]["bpp"], 5)
     print(json.dumps(out))
 
 
@@ -295,9 +301,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default=None,
+    ap.add_argument("--precision", choices=["fp32", "bf16", "fp8"], default=None,
                     help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
-                         "bf16 for the batched workload")
+                         "bf16 for the batched and serving workloads")
     ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix",
                                            "precision_report"],
                     default="ycbcr512x768")
@@ -327,8 +333,7 @@ def main():
     cfg = get_config("ycbcr512x768")
     H, W, N = cfg["H"], cfg["W"], cfg["planes"]
     w = make_weights(cfg)
-    from paper_2405_12631_amd import WV_BF16, WV_FP32
-    prec = WV_BF16 if args.precision == "bf16" else WV_FP32
+    prec = _precision(args.precision)
     model = codec.Model(cfg, pack_weights(cfg, w), precision=prec)
     x = sinusoid_1f_planes(H, W, planes=N, seed=cfg["seed_image"])
     ws = codec.Workspace(model, N, H, W)
@@ -391,7 +396,8 @@ def main():
     ctx_time = ctx_ms.sum(axis=1).mean() * 1e-3
     n_ctx_launch = nsub * (cfg["ctx_layers"] * 4) + nsub      # step layers + one LSTM per subband
     peak = MFMA_PEAK_TFLOPS[args.precision]
-    kname = "conv3x3_mfma_bf16" if args.precision == "bf16" else "conv3x3_mfma_f32"
+    kname = {"fp32": "conv3x3_mfma_f32", "bf16": "conv3x3_mfma_bf16",
+             "fp8": "conv3x3_mfma_bf16 (e4m3 form)"}[args.precision]
     roof = dict(bound="mfma", achieved=round(ctx_flops / ctx_time / 1e12, 3),
                 peak=peak, unit="TFLOP/s",
                 frac=round(ctx_flops / ctx_time / 1e12 / peak, 4), traffic=None,
@@ -403,7 +409,8 @@ def main():
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
         value=round(mpx, 4), unit="Mpixel/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(ms_step, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32" if args.precision == "fp32" else "bf16 context convs (fp32 accumulate), fp32 lifting/cdf",
+        dtype="f32" if args.precision == "fp32" else
+        f"{args.precision} context convs (fp32 accumulate), fp32 lifting/cdf",
         data="synthetic",
         config=dict(workload="ycbcr512x768: one 512x768 3-plane YCbCr image, 1/f sinusoids + noise "
                              "(seed 2), 4-level CNN lifting (32 ch), 64-ch 4-layer context stacks, "

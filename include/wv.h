@@ -50,6 +50,13 @@ enum {
     WV_ENOMEM = -7        /* caller-provided buffer too small */
 };
 
+/* Arithmetic of the context-model convolutions (ConvLSTM and step stacks; the
+ * lifting transform, the mixture head's epilogue and the CDF tables are FP32 in
+ * every mode).  WV_BF16: BF16 operands and activations, FP32 accumulation.
+ * WV_FP8: e4m3 weights with one FP32 scale per output channel (scale = max |w|
+ * of the channel / 448), e4m3 activations (unscaled, saturated at +-448),
+ * FP32 accumulation, symbols fed through a BF16 chunk so they stay exact.
+ * Reduced precision needs ctx_ch of 32 or 64 and ctx_arch 0. */
 typedef enum { WV_FP32 = 0, WV_BF16 = 1, WV_FP8 = 2 } wv_precision;
 
 /* Component family of the per-coefficient mixture.  Sec. 3.1 uses a Laplacian
@@ -328,6 +335,34 @@ int wv_impulse_responses(const wv_model* m, const int16_t* d_q, int H, int W, fl
  */
 int wv_temporal_haar_forward(float* d_frames, int T, long long n, void* stream);
 int wv_temporal_haar_inverse(float* d_frames, int T, long long n, void* stream);
+
+/*
+ * Lossless trim of CDF rows for the copy to the host coder (the tables of
+ * wv_cdf_tables, Sec. 3.1).  With F_j = cdf[j] - j (j = 1 .. nsym-1), F is
+ * non-decreasing, 0 below the row's probability-mass window and F_max - 1
+ * above it (F_max = 2^16 - nsym; the upper tail always keeps one count), so a
+ * row is fixed by
+ *   lo  = 1 + #{j : F_j = 0},   len = #{j : 0 < F_j < F_max - 1},
+ * and F_lo .. F_{lo+len-1}.  wv_cdf_trim (device, stream-ordered) writes
+ * d_lolen uint8 [n][2] = (lo, len) and the rows' F values back to back in row
+ * order into d_packed (uint16; packed_cap >= n (nsym - 1), the worst case; only
+ * the first sum(len) entries are written).  d_scratch: device buffer of
+ * wv_cdf_trim_scratch_bytes(n) bytes.  The host recovers the offsets from the
+ * lengths, so a copy needs 2 n + 2 sum(len) bytes instead of 2 n (nsym + 1).
+ * wv_cdf_untrim (host) rebuilds the full tables (WV_ECORRUPT if (lo, len) are
+ * out of range or sum(len) != packed_count).  wv_rans_encode_trim /
+ * wv_rans_decode_trim: the coder below driven by trimmed tables; identical
+ * streams and symbols to the full-table calls.
+ */
+int wv_cdf_trim_scratch_bytes(long long n, size_t* bytes);
+int wv_cdf_trim(const uint16_t* d_cdf, long long n, int nsym, uint8_t* d_lolen, uint16_t* d_packed,
+                long long packed_cap, void* d_scratch, size_t scratch_bytes, void* stream);
+int wv_cdf_untrim(const uint8_t* lolen, const uint16_t* packed, long long packed_count, int nsym,
+                  long long n, uint16_t* cdf_out);
+int wv_rans_encode_trim(const uint8_t* lolen, const uint16_t* packed, long long packed_count, int nsym,
+                        const uint8_t* sym, long long n, uint8_t* out, size_t cap, size_t* len);
+int wv_rans_decode_trim(const uint8_t* lolen, const uint16_t* packed, long long packed_count, int nsym,
+                        long long n, const uint8_t* in, size_t len, uint8_t* sym_out);
 
 /*
  * Host rANS coder (no GPU).  Byte-wise renormalising rANS with a 32-bit state

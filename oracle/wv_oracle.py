@@ -530,6 +530,44 @@ def cdf_to_u16(cdf):
     return (np.asarray(cdf, np.int64) % 65536).astype(np.uint16)
 
 
+def cdf_trim(cdf):
+    """Lossless trim of integer CDF rows [n][N_s + 1] (entry N_s = T), written from the
+    table definition of cdf_tables: F_j = cdf[j] - j is 0 below each row's mass window
+    and F_max - 1 above it (the upper-tail ceiling is at least 1), so a row is
+    (lo, len, F_lo .. F_{lo+len-1}) with lo = 1 + the number of j in 1 .. N_s-1 with
+    F_j = 0 and len = the number with 0 < F_j < F_max - 1.
+    Returns (lolen int [n][2], packed int [sum len])."""
+    cdf = np.asarray(cdf, np.int64)
+    n, E = cdf.shape
+    ns = E - 1
+    T = int(cdf[0, -1]) if n else 65536
+    fmax = T - ns
+    lolen = np.zeros((n, 2), np.int64)
+    parts = []
+    for r in range(n):
+        F = [int(cdf[r, j]) - j for j in range(1, ns)]
+        zeros = sum(1 for v in F if v == 0)
+        mid = [v for v in F if 0 < v < fmax - 1]
+        lolen[r] = (1 + zeros, len(mid))
+        parts.append(np.asarray(mid, np.int64))
+    packed = np.concatenate(parts) if parts else np.zeros(0, np.int64)
+    return lolen, packed
+
+
+def cdf_untrim(lolen, packed, n_sym, T=65536):
+    """Inverse of cdf_trim: rows [n][n_sym + 1] with entry n_sym = T."""
+    lolen = np.asarray(lolen, np.int64)
+    out = np.zeros((len(lolen), n_sym + 1), np.int64)
+    off = 0
+    for r, (lo, ln) in enumerate(lolen):
+        for j in range(n_sym):
+            F = 0 if j < lo else int(packed[off + j - lo]) if j < lo + ln else T - n_sym - 1
+            out[r, j] = j + F
+        out[r, n_sym] = T
+        off += ln
+    return out
+
+
 def ideal_bits(cdf, idx):
     """sum -log2(freq / T) of symbol indices idx under rows cdf (int, entry N_s = T)."""
     cdf = np.asarray(cdf, np.int64)

@@ -102,6 +102,12 @@ class Workspace:
         self.params = torch.empty(N * maxg * 3 * K, dtype=torch.float32, device=model.device)
         self.cdf = torch.empty(N * maxg * (model.nsym + 1), dtype=torch.int16, device=model.device)
         self.sym = torch.empty(N * maxg, dtype=torch.uint8, device=model.device)
+        # trimmed copy of the CDF rows for the host coder (wv_cdf_trim)
+        tb = ctypes.c_size_t()
+        L.call("wv_cdf_trim_scratch_bytes", N * maxg, _byref(tb))
+        self.lolen = torch.empty(2 * N * maxg, dtype=torch.uint8, device=model.device)
+        self.packed = torch.empty(N * maxg * (model.nsym - 1), dtype=torch.int16, device=model.device)
+        self.trim_scratch = torch.empty(max(tb.value, 8), dtype=torch.uint8, device=model.device)
 
 
 # ---------------------------------------------------------------------------
@@ -142,6 +148,40 @@ def cdf_tables(model, params, out=None):
     L.call("wv_cdf_tables", _ptr(params), n, K, model.c.dist, model.cfg["sym_min"],
            model.cfg["sym_max"], model.cfg["cdf_bits"], _ptr(out), _stream())
     return out[:n * (model.nsym + 1)].view(n, model.nsym + 1)
+
+
+class Trimmed:
+    """Host copy of trimmed CDF rows: lolen uint8 [n, 2], packed uint16 [sum len] and the
+    row offsets into packed."""
+
+    def __init__(self, lolen, packed, nsym):
+        self.lolen = np.ascontiguousarray(lolen, np.uint8).reshape(-1, 2)
+        self.packed = np.ascontiguousarray(packed, np.uint16)
+        self.nsym = nsym
+        self.off = np.zeros(len(self.lolen) + 1, np.int64)
+        np.cumsum(self.lolen[:, 1], out=self.off[1:])
+
+    def rows(self, a, b):
+        """Rows a..b-1 as (lolen, packed) slices."""
+        return self.lolen[a:b], self.packed[self.off[a]:self.off[b]]
+
+    def full(self):
+        n = len(self.lolen)
+        out = np.empty((n, self.nsym + 1), np.uint16)
+        L.call("wv_cdf_untrim", self.lolen.ctypes.data, self.packed.ctypes.data, self.packed.size, self.nsym, n,
+               out.ctypes.data)
+        return out
+
+
+def cdf_trim_to_host(model, cdf, ws):
+    """Trim device CDF rows [n, nsym+1] and copy them to the host: 2 n + 2 sum(len) bytes."""
+    n = cdf.shape[0]
+    L.call("wv_cdf_trim", _ptr(cdf), n, model.nsym, _ptr(ws.lolen), _ptr(ws.packed), ws.packed.numel(),
+           _ptr(ws.trim_scratch), ws.trim_scratch.numel(), _stream())
+    lolen = ws.lolen[:2 * n].cpu().numpy()
+    total = int(lolen[1::2].astype(np.int64).sum())
+    packed = ws.packed[:total].cpu().numpy().view(np.uint16)
+    return Trimmed(lolen, packed, model.nsym)
 
 
 def scatter_symbols(model, sym, q, ws, i, g):
@@ -264,6 +304,31 @@ def rans_encode(cdf_u16, sym_u8, nsym):
     return buf[:ln.value].tobytes()
 
 
+def rans_encode_trim(tr, a, b, sym_u8):
+    """Encode rows a..b-1 of a Trimmed table set."""
+    lolen, packed = tr.rows(a, b)
+    sym_u8 = np.ascontiguousarray(sym_u8, np.uint8)
+    n = sym_u8.size
+    cap = 16 + 4 * n
+    buf = np.empty(cap, np.uint8)
+    ln = ctypes.c_size_t()
+    pk = packed if packed.size else np.zeros(1, np.uint16)
+    L.call("wv_rans_encode_trim", lolen.ctypes.data, pk.ctypes.data, packed.size, tr.nsym, sym_u8.ctypes.data, n,
+           buf.ctypes.data, cap, _byref(ln))
+    return buf[:ln.value].tobytes()
+
+
+def rans_decode_trim(tr, a, b, data):
+    lolen, packed = tr.rows(a, b)
+    n = b - a
+    out = np.empty(n, np.uint8)
+    src = np.frombuffer(data, np.uint8) if len(data) else np.zeros(1, np.uint8)
+    pk = packed if packed.size else np.zeros(1, np.uint16)
+    L.call("wv_rans_decode_trim", lolen.ctypes.data, pk.ctypes.data, packed.size, tr.nsym, n, src.ctypes.data,
+           len(data), out.ctypes.data)
+    return out
+
+
 def rans_decode(cdf_u16, data, n, nsym):
     cdf_u16 = np.ascontiguousarray(cdf_u16, np.uint16)
     out = np.empty(n, np.uint8)
@@ -335,21 +400,19 @@ def encode(model, planes, ws=None):
             context_params(model, q, ws, 0, 0)          # advances the long context only
             cdf = cdf_tables(model, ar_params(model, q, ws), out=ws.cdf)
             n0 = s["h"] * s["w"]
-            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            tr = cdf_trim_to_host(model, cdf, ws)
             sym_h = (q[:, :n0].cpu().numpy().astype(np.int32) - model.cfg["sym_min"]).astype(np.uint8)
             for n in range(N):
-                streams[n][0] = [rans_encode(cdf_h[n * n0:(n + 1) * n0], sym_h[n], model.nsym),
-                                 b"", b"", b""]
+                streams[n][0] = [rans_encode_trim(tr, n * n0, (n + 1) * n0, sym_h[n]), b"", b"", b""]
             continue
         for g in range(4):
             prm = context_params(model, q, ws, i, g)
             cdf = cdf_tables(model, prm, out=ws.cdf)
             sym = gather_symbols(model, q, ws, i, g, out=ws.sym)
-            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            tr = cdf_trim_to_host(model, cdf, ws)
             sym_h = sym.cpu().numpy()
             ng = sym_h.shape[1]
-            futs = [_pool.submit(rans_encode, cdf_h[n * ng:(n + 1) * ng], sym_h[n], model.nsym)
-                    for n in range(N)]
+            futs = [_pool.submit(rans_encode_trim, tr, n * ng, (n + 1) * ng, sym_h[n]) for n in range(N)]
             for n, f in enumerate(futs):
                 streams[n][i][g] = f.result()
     return pack_stream(model, N, H, W, streams), q
@@ -368,10 +431,9 @@ def decode(model, data, ws=None, want_u8=True):
         for g in range(4):
             prm = context_params(model, q, ws, i, g)
             cdf = cdf_tables(model, prm, out=ws.cdf)
-            cdf_h = cdf.cpu().numpy().view(np.uint16)
+            tr = cdf_trim_to_host(model, cdf, ws)
             ng = Model.group_count(s["h"], s["w"], g)
-            futs = [_pool.submit(rans_decode, cdf_h[n * ng:(n + 1) * ng], streams[n][i][g], ng,
-                                 model.nsym) for n in range(N)]
+            futs = [_pool.submit(rans_decode_trim, tr, n * ng, (n + 1) * ng, streams[n][i][g]) for n in range(N)]
             sym_h = np.stack([f.result() for f in futs]) if N else np.zeros((0, ng), np.uint8)
             sym = ws.sym[:N * ng]
             sym.copy_(torch.from_numpy(sym_h.reshape(-1)))

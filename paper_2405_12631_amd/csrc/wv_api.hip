@@ -2,6 +2,8 @@
 // documentation in include/wv.h).  Host code: argument checks, weight
 // repacking, workspace layout and the launch sequence of each call.
 #include <stdarg.h>
+#include <algorithm>
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -145,7 +147,7 @@ struct PackBuf {
     }
 };
 
-struct MfmaRef { size_t w, wsym, bias; int cin, cout, nbt, has_sym, taps; };
+struct MfmaRef { size_t w, wsym, bias, scale; int cin, cout, nbt, has_sym, taps; };
 struct VecRef { size_t w, bias; int ch; };
 
 // Original output channel of packed column nc.  LSTM: columns are grouped by
@@ -159,7 +161,7 @@ static int perm_col(int nc, int C, bool lstm) {
 
 MfmaRef pack_mfma(PackBuf& pb, const float* blob, const ConvShape& s, int has_sym, bool lstm,
                   int C) {
-    MfmaRef r;
+    MfmaRef r{};
     r.cin = s.cin - has_sym;
     r.cout = s.cout;
     r.nbt = (s.cout + 15) / 16;
@@ -219,7 +221,7 @@ static uint16_t host_f2bf(float f) {   // round to nearest even
 // Stored in the float pack buffer; offsets count floats, so 2 bf16 per float.
 MfmaRef pack_mfma16(PackBuf& pb, const float* blob, const ConvShape& s, int has_sym, bool lstm,
                     int C) {
-    MfmaRef r;
+    MfmaRef r{};
     r.cin = s.cin - has_sym;
     r.cout = s.cout;
     r.nbt = (s.cout + 15) / 16;
@@ -257,6 +259,92 @@ MfmaRef pack_mfma16(PackBuf& pb, const float* blob, const ConvShape& s, int has_
                     float v = 0.f;
                     if (tap < 9 && nc < s.cout)
                         v = W[((long long)perm_col(nc, C, lstm) * cin_total + 0) * 9 + tap];
+                    ps[((size_t)nb * 64 + lane) * 8 + j] = host_f2bf(v);
+                }
+    }
+    float* pbias = pb.data.data() + r.bias;
+    for (int nc = 0; nc < s.cout; ++nc) pbias[nc] = B[perm_col(nc, C, lstm)];
+    return r;
+}
+
+// float -> OCP e4m3 (bias 7, 3 mantissa bits, no infinities, largest finite
+// 448), round to nearest even, saturating.
+static uint8_t host_f2e4m3(float f) {
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0;
+    double a = std::fabs((double)f);
+    if (std::isnan(f)) return 0x7f;
+    if (a >= 448.0) return sign | 0x7e;
+    if (a < std::ldexp(1.0, -6)) {                     // subnormal: multiples of 2^-9
+        const double m = std::nearbyint(a * 512.0);     // ties to even (default rounding)
+        return sign | (uint8_t)m;                        // m == 8 is the smallest normal
+    }
+    int e;
+    const double fr = std::frexp(a, &e);                // a = fr 2^e, fr in [0.5, 1)
+    double m = std::nearbyint((fr * 2.0 - 1.0) * 8.0);  // mantissa of 1.m x 2^(e-1)
+    int ex = e - 1 + 7;
+    if (m == 8.0) {
+        m = 0.0;
+        ++ex;
+    }
+    if (ex > 15 || (ex == 15 && m == 7.0)) return sign | 0x7e;
+    return sign | (uint8_t)((ex << 3) | (int)m);
+}
+
+// FP8 layer: e4m3 B fragments of 8 consecutive K per lane (K chunk = 32
+// channels, the BF16 order with bytes for elements), one FP32 scale per packed
+// output column: scale = max |w| of the column / 448, w8 = e4m3(w / scale).  The
+// symbol-channel chunk stays BF16 (divided by the same scale).
+MfmaRef pack_mfma8(PackBuf& pb, const float* blob, const ConvShape& s, int has_sym, bool lstm, int C) {
+    MfmaRef r{};
+    r.cin = s.cin - has_sym;
+    r.cout = s.cout;
+    r.nbt = (s.cout + 15) / 16;
+    r.has_sym = has_sym;
+    r.taps = 9;
+    const int CC = r.cin / 32;
+    const int cin_total = s.cin;
+    const float* W = blob + s.w_off;
+    const float* B = blob + s.b_off;
+    r.w = pb.add((size_t)9 * CC * r.nbt * 64 * 2);          // 8 bytes = 2 floats per lane
+    r.wsym = has_sym ? pb.add((size_t)r.nbt * 64 * 4) : 0;
+    r.bias = pb.add((size_t)r.nbt * 16);
+    r.scale = pb.add((size_t)r.nbt * 16);
+    float* psc = pb.data.data() + r.scale;
+    for (int nc = 0; nc < r.nbt * 16; ++nc) {
+        float mx = 0.f;
+        if (nc < s.cout) {
+            const int o = perm_col(nc, C, lstm);
+            for (int k = 0; k < r.cin; ++k)
+                for (int tap = 0; tap < 9; ++tap)
+                    mx = std::max(mx, std::fabs(W[((long long)o * cin_total + has_sym + k) * 9 + tap]));
+        }
+        psc[nc] = mx > 0.f ? mx / 448.f : 1.f;
+    }
+    uint8_t* pw = reinterpret_cast<uint8_t*>(pb.data.data() + r.w);
+    for (int tap = 0; tap < 9; ++tap)
+        for (int cc = 0; cc < CC; ++cc)
+            for (int nb = 0; nb < r.nbt; ++nb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 8; ++j) {
+                        const int kk = lane >> 4, nn = lane & 15;
+                        const int k = 32 * cc + 8 * kk + j;
+                        const int nc = nb * 16 + nn;
+                        float v = 0.f;
+                        if (nc < s.cout)
+                            v = W[((long long)perm_col(nc, C, lstm) * cin_total + has_sym + k) * 9 + tap] / psc[nc];
+                        pw[((((size_t)(tap * CC + cc) * r.nbt + nb) * 64 + lane) * 8) + j] = host_f2e4m3(v);
+                    }
+    if (has_sym) {
+        uint16_t* ps = reinterpret_cast<uint16_t*>(pb.data.data() + r.wsym);
+        for (int nb = 0; nb < r.nbt; ++nb)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int j = 0; j < 8; ++j) {
+                    const int kk = lane >> 4, nn = lane & 15;
+                    const int tap = 8 * kk + j;
+                    const int nc = nb * 16 + nn;
+                    float v = 0.f;
+                    if (tap < 9 && nc < s.cout)
+                        v = W[((long long)perm_col(nc, C, lstm) * cin_total + 0) * 9 + tap] / psc[nc];
                     ps[((size_t)nb * 64 + lane) * 8 + j] = host_f2bf(v);
                 }
     }
@@ -318,7 +406,7 @@ HostModel pack_all(PackBuf& pb, const float* blob, const wv_config& c, int preci
             hm.lift_mid[f].push_back(pack_mfma(pb, blob, v[l], 0, false, 0));
         hm.lift_last[f] = pack_vec_last(pb, blob, v.back());
     }
-    auto ctxpack = precision == WV_BF16 ? pack_mfma16 : pack_mfma;
+    auto ctxpack = precision == WV_BF16 ? pack_mfma16 : precision == WV_FP8 ? pack_mfma8 : pack_mfma;
     hm.lstm = ctxpack(pb, blob, mf.lstm, 1, true, c.ctx_ch);
     for (int t = 0; t < 4; ++t)
         for (int g = 0; g < 4; ++g) {
@@ -394,9 +482,10 @@ struct wv_model {
 
 static int check_precision(const wv_config* c, int precision) {
     if (precision == WV_FP32) return WV_OK;
-    if (precision == WV_BF16) {
-        if (c->ctx_ch % 32) return fail(WV_EUNSUPPORTED, "BF16 context needs ctx_ch of 32 or 64");
-        if (c->ctx_arch != 0) return fail(WV_EUNSUPPORTED, "BF16 context needs ctx_arch 0");
+    if (precision == WV_BF16 || precision == WV_FP8) {
+        const char* nm = precision == WV_BF16 ? "BF16" : "FP8";
+        if (c->ctx_ch % 32) return fail(WV_EUNSUPPORTED, "%s context needs ctx_ch of 32 or 64", nm);
+        if (c->ctx_arch != 0) return fail(WV_EUNSUPPORTED, "%s context needs ctx_arch 0", nm);
         return WV_OK;
     }
     return fail(WV_EUNSUPPORTED, "precision %d is not implemented", precision);
@@ -460,7 +549,8 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
     auto mfma16 = [&](const MfmaRef& r) {
         return MfmaLayer16{reinterpret_cast<const uint16_t*>(base + r.w),
                            r.has_sym ? reinterpret_cast<const uint16_t*>(base + r.wsym) : nullptr,
-                           base + r.bias, r.cin, r.cout, r.nbt, r.has_sym};
+                           base + r.bias, r.scale ? base + r.scale : nullptr, r.cin, r.cout, r.nbt,
+                           r.has_sym};
     };
     wv_model* m = new wv_model();
     m->cfg = *cfg;
@@ -470,7 +560,7 @@ extern "C" int wv_model_create(const wv_config* cfg, const float* d_weights, lon
         m->lift_last[f] = vec(hm.lift_last[f]);
         for (auto& r : hm.lift_mid[f]) m->lift_mid[f].push_back(mfma(r));
     }
-    if (precision == WV_BF16) {
+    if (precision != WV_FP32) {
         m->lstm16 = mfma16(hm.lstm);
         for (int t = 0; t < 4; ++t)
             for (int g = 0; g < 4; ++g)
@@ -888,7 +978,7 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
     if (ng == 0) return WV_OK;   // a 1-wide subband has no positions at this step
     hipStream_t s = (hipStream_t)stream;
     const int C = m->cfg.ctx_ch;
-    const bool bf16 = m->precision == WV_BF16;   // h and activations stored as BF16
+    const bool bf16 = m->precision != WV_FP32;   // h and activations stored as BF16 or FP8
     const long long HW = (long long)H * W;
     const size_t SS = state_floats(m->cfg, N, H, W);
     const Sub& S = lay[i];
@@ -1062,6 +1152,25 @@ extern "C" int wv_cdf_tables(const float* d_params, long long n, int K, int dist
     return WV_OK;
 }
 
+extern "C" int wv_cdf_trim_scratch_bytes(long long n, size_t* bytes) {
+    if (n < 0 || !bytes) return fail(WV_EINVAL, "bad argument");
+    *bytes = cdf_trim_scratch_bytes(n);
+    return WV_OK;
+}
+
+extern "C" int wv_cdf_trim(const uint16_t* d_cdf, long long n, int nsym, uint8_t* d_lolen, uint16_t* d_packed,
+                           long long packed_cap, void* d_scratch, size_t scratch_bytes, void* stream) {
+    if (n < 0) return fail(WV_ESHAPE, "negative row count");
+    if (nsym < 2 || nsym > 255) return fail(WV_EUNSUPPORTED, "alphabet must have 2..255 symbols");
+    if (n == 0) return WV_OK;
+    if (!d_cdf || !d_lolen || !d_packed || !d_scratch) return fail(WV_EINVAL, "null pointer");
+    if (packed_cap < n * (long long)(nsym - 1)) return fail(WV_ENOMEM, "packed buffer below n (nsym - 1)");
+    if (scratch_bytes < cdf_trim_scratch_bytes(n)) return fail(WV_ENOMEM, "scratch below wv_cdf_trim_scratch_bytes");
+    HIPCHK(launch_cdf_trim(d_cdf, n, nsym, d_lolen, d_packed, reinterpret_cast<long long*>(d_scratch),
+                           (hipStream_t)stream));
+    return WV_OK;
+}
+
 static int sym_io(const wv_config* cfg, int N, int H, int W, int i, int g, std::vector<Sub>& lay) {
     int rc = check_cfg(cfg);
     if (rc) return rc;
@@ -1140,7 +1249,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
     if (!m) return fail(WV_EINVAL, "null model");
     if (ng < 1 || !groups) return fail(WV_EINVAL, "no groups");
     if (m->cfg.ctx_arch != 0) return fail(WV_EUNSUPPORTED, "plans need ctx_arch 0");
-    const bool bf16 = m->precision == WV_BF16;
+    const bool bf16 = m->precision != WV_FP32;   // BF16 or FP8 kernels
     const int C = m->cfg.ctx_ch;
     const int J = m->cfg.levels;
     const int nsub = 3 * J + 1;
@@ -1344,7 +1453,7 @@ extern "C" int wv_plan_context_params(const wv_plan* p, int i, int g, void* stre
     const int nsub = (int)p->lay[0].size();
     if (i < 0 || i >= nsub || g < 0 || g > 3) return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
     hipStream_t s = (hipStream_t)stream;
-    const bool bf16 = p->m->precision == WV_BF16;
+    const bool bf16 = p->m->precision != WV_FP32;   // BF16 or FP8 kernels
     for (const PlanLaunch& pl : p->steps[i * 4 + g]) {
         if (bf16)
             HIPCHK(launch_conv_seg_bf16(reinterpret_cast<const ConvSeg16*>(p->d_desc + pl.seg_off), pl.nseg,
@@ -1426,7 +1535,7 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     if (!m) return fail(WV_EINVAL, "null model");
     if (n < 0 || (n > 0 && !items)) return fail(WV_EINVAL, "bad item list");
     if (m->cfg.ctx_arch != 0) return fail(WV_EUNSUPPORTED, "items need ctx_arch 0");
-    const bool bf16 = m->precision == WV_BF16;
+    const bool bf16 = m->precision != WV_FP32;   // BF16 or FP8 kernels
     const int C = m->cfg.ctx_ch;
     const int Lc = m->cfg.ctx_layers;
     const int th = conv_tile_h(bf16), tw = conv_tile_w(bf16);

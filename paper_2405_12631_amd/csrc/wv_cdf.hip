@@ -77,4 +77,108 @@ hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smi
     return hipErrorInvalidValue;
 }
 
+
+// ---- lossless trim of CDF rows (for the copy to the host coder) ----------
+// In a row, F_j = cdf[j] - j (j = 1 .. nsym-1) is non-decreasing, 0 below the
+// mass window and F_max - 1 above it (F_max = 2^16 - nsym; the upper tail keeps
+// at least one count, so F never reaches F_max).  The row is therefore fixed by
+// lo = 1 + #{F_j = 0}, len = #{0 < F_j < F_max - 1} and F_lo .. F_{lo+len-1};
+// both counts come from binary searches.  Rows go 256 to a block: the first kernel
+// writes (lo, len) and the block's sum of len, the second scans the block sums,
+// the third writes each row's F values at its offset.
+namespace {
+
+__global__ __launch_bounds__(256) void trim_len_k(const uint16_t* __restrict__ cdf, long long n, int nsym,
+                                                  uint8_t* __restrict__ lolen, long long* __restrict__ bsum) {
+    __shared__ int red[256];
+    const long long row = (long long)blockIdx.x * 256 + threadIdx.x;
+    int len = 0;
+    if (row < n) {
+        const uint16_t* r = cdf + row * (nsym + 1);
+        const int ftop = 65536 - nsym - 1;   // F_max - 1
+        // first j in [1, nsym) with F_j > 0 (nsym if none)
+        int a = 1, b = nsym;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if ((int)r[mid] - mid > 0) b = mid; else a = mid + 1;
+        }
+        const int lo = a;
+        // first j in [lo, nsym) with F_j == F_max - 1 (nsym if none)
+        b = nsym;
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if ((int)r[mid] - mid >= ftop) b = mid; else a = mid + 1;
+        }
+        len = a - lo;
+        lolen[2 * row] = (uint8_t)lo;
+        lolen[2 * row + 1] = (uint8_t)len;
+    }
+    red[threadIdx.x] = len;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of nb block sums in place (one workgroup, chunks of 1024).
+__global__ __launch_bounds__(1024) void trim_scan_k(long long* __restrict__ bsum, long long nb) {
+    __shared__ long long sh[1024];
+    long long carry = 0;
+    for (long long base = 0; base < nb; base += 1024) {
+        const long long i = base + threadIdx.x;
+        const long long v = i < nb ? bsum[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan
+            const long long add = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+        const long long tot = sh[1023];
+        __syncthreads();
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void trim_write_k(const uint16_t* __restrict__ cdf, long long n, int nsym,
+                                                    const uint8_t* __restrict__ lolen,
+                                                    const long long* __restrict__ bsum,
+                                                    uint16_t* __restrict__ packed) {
+    __shared__ int sh[256];
+    const long long row = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int len = row < n ? lolen[2 * row + 1] : 0;
+    sh[threadIdx.x] = len;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int add = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (row < n) {
+        const long long off = bsum[blockIdx.x] + sh[threadIdx.x] - len;
+        const int lo = lolen[2 * row];
+        const uint16_t* r = cdf + row * (nsym + 1);
+        for (int t = 0; t < len; ++t) packed[off + t] = (uint16_t)(r[lo + t] - (lo + t));
+    }
+}
+
+}  // namespace
+
+size_t cdf_trim_scratch_bytes(long long n) { return (size_t)((n + 255) / 256) * sizeof(long long); }
+
+hipError_t launch_cdf_trim(const uint16_t* cdf, long long n, int nsym, uint8_t* lolen, uint16_t* packed,
+                           long long* scratch, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256;
+    hipLaunchKernelGGL(trim_len_k, dim3((unsigned)nb), dim3(256), 0, s, cdf, n, nsym, lolen, scratch);
+    hipLaunchKernelGGL(trim_scan_k, dim3(1), dim3(1024), 0, s, scratch, nb);
+    hipLaunchKernelGGL(trim_write_k, dim3((unsigned)nb), dim3(256), 0, s, cdf, n, nsym, lolen, scratch, packed);
+    return hipGetLastError();
+}
+
 }  // namespace wv

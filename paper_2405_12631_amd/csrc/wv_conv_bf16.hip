@@ -1,5 +1,6 @@
-// 3x3 convolution as an implicit GEMM on the gfx950 matrix cores, BF16
-// operands with FP32 accumulation (precision variant of the context model).
+// 3x3 convolution as an implicit GEMM on the gfx950 matrix cores with BF16 or
+// FP8 (e4m3) operands and FP32 accumulation (precision variants of the context
+// model).
 //
 // Same GEMM view and epilogues as the FP32 kernel (wv_conv.hip); what changes
 // with v_mfma_f32_16x16x32_bf16 is the balance: one instruction covers 32
@@ -10,6 +11,13 @@
 // B fragments: per-tap weight slices staged in LDS, double buffered, fetched
 // into registers one tap ahead.  Activations in and out are BF16 (NHWC), the
 // LSTM cell state, every epilogue and the mixture parameters are FP32.
+//
+// FP8 form (F8): the same tiling on v_mfma_f32_16x16x32_fp8_fp8, one 8-byte
+// fragment (8 channels) per lane, activations stored as e4m3 bytes, weights
+// e4m3 with one FP32 scale per output channel applied to the accumulator
+// before the bias.  The symbol channel keeps its BF16 MFMA chunk (its weights
+// are packed divided by the channel scale), so symbols up to the int16 range
+// stay exact.
 #include "wv_device.h"
 #include "wv_internal.h"
 
@@ -35,18 +43,46 @@ __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
 
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-template <int CIN, int NB, bool SYM, int MODE>
+// float -> e4m3 byte, round to nearest even, saturated to +-448 first.
+__device__ __forceinline__ uint8_t f2e4m3(float f) {
+    f = fminf(fmaxf(f, -448.f), 448.f);
+    return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false) & 0xff);
+}
+
+template <bool F8>
+struct Frag;
+template <>
+struct Frag<false> { using T = uint4; };   // 8 bf16
+template <>
+struct Frag<true> { using T = uint2; };    // 8 e4m3
+
+template <bool F8>
+__device__ __forceinline__ floatx4 mfma_lp(const typename Frag<F8>::T& a, const typename Frag<F8>::T& b,
+                                           const floatx4& c) {
+    if constexpr (F8)
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b),
+                                                          c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
+}
+
+template <int CIN, int NB, bool SYM, int MODE, bool F8>
 __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvArgs& a, const int tile_idx,
                                                const int ycol) {
-    constexpr int STRIDE = CIN + 8;          // bf16 elements per halo position (conflict-free)
-    constexpr int CC = CIN / 32;             // 32-channel K chunks per tap
-    constexpr int BV = CC * NB * 64;         // uint4 of B per tap for this workgroup
+    using FragT = typename Frag<F8>::T;
+    constexpr int ES = F8 ? 1 : 2;              // bytes per activation element
+    constexpr int FB = 8 * ES;                  // bytes per operand fragment (8 K values)
+    constexpr int STRIDE = CIN * ES + 8 * ES;   // bytes per halo position (conflict-free reads)
+    constexpr int CC = CIN / 32;                // 32-channel K chunks per tap
+    constexpr int BU = FB * 64 / 16;            // uint4 per (chunk, 16-column block) of B
+    constexpr int BV = CC * NB * BU;            // uint4 of B per tap for this workgroup
     constexpr int BPT = (BV + 255) / 256;
     constexpr int MB = (MODE == CONV_HEAD) ? 2 : 4;   // head: only the rows of its step's parity
+    constexpr int OS = NB * 16 * ES + 16;       // bytes per position of the staged output tile
     static_assert(BPT <= 2, "B slice too large");
-    // Input halo; after the MFMA loop it holds the output tile (RELU epilogue).
-    constexpr int LDS_IN = HALO * STRIDE > TH * TW * (NB * 16 + 8) ? HALO * STRIDE : TH * TW * (NB * 16 + 8);
-    __shared__ __attribute__((aligned(16))) uint16_t lds_in[LDS_IN];
+    // Input halo; after the MFMA loop it holds the output tile (RELU/TANH epilogue).
+    constexpr int LDS_IN = HALO * STRIDE > TH * TW * OS ? HALO * STRIDE : TH * TW * OS;
+    __shared__ __attribute__((aligned(16))) uint8_t lds_in[LDS_IN];
     __shared__ __attribute__((aligned(16))) uint4 lds_w[2][BV];
     __shared__ __attribute__((aligned(16))) uint4 lds_ws[SYM ? NB * 64 : 1];
     __shared__ uint16_t lds_s[SYM ? HALO : 1];
@@ -69,13 +105,13 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     const uint4* wg = reinterpret_cast<const uint4*>(L.w);
     auto boff_of = [&](int k) -> long long {
         const int idx = (tid + k * 256) < BV ? tid + k * 256 : 0;
-        const int cc = idx / (NB * 64);
-        const int rem = idx - cc * (NB * 64);
-        return ((long long)cc * L.nbt + nblk0 + (rem >> 6)) * 64 + (rem & 63);
+        const int cc = idx / (NB * BU);
+        const int rem = idx - cc * (NB * BU);
+        return ((long long)cc * L.nbt + nblk0) * BU + rem;
     };
     const long long bo0 = boff_of(0);
     const long long bo1 = BPT > 1 ? boff_of(1) : 0;
-    const long long btap = (long long)CC * L.nbt * 64;
+    const long long btap = (long long)CC * L.nbt * BU;
     uint4 b0, b1;
 #define WV_LOAD_B(tp)                                       \
     {                                                       \
@@ -92,29 +128,36 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 
     {
         const int win = a.w >> a.in_up;
-        const uint16_t* inp = a.in16 ? a.in16 + (long long)n * a.in_ps : nullptr;
-        constexpr int V = CIN / 8;                   // uint4 per position
+        const uint8_t* inp =
+            a.in16 ? reinterpret_cast<const uint8_t*>(a.in16) + (long long)n * a.in_ps * ES : nullptr;
+        constexpr int V = CIN * ES / 16;             // uint4 per position
         constexpr int NH = (HALO * V + 255) / 256;   // per thread: all loads in flight before any store
         uint4 hv[NH];
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             const int idx = tid + k * 256;
             const int pos = idx / V;
-            const int c8 = idx - pos * V;
+            const int c16 = idx - pos * V;
             const int hy = pos / HWD;
             const int r = r0 + hy - 1;
             const int c = c0 + (pos - hy * HWD) - 1;
             hv[k] = make_uint4(0, 0, 0, 0);
             if (idx < HALO * V && inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
                 hv[k] = *reinterpret_cast<const uint4*>(
-                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c8 * 8);
+                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN * ES + c16 * 16);
         }
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             const int idx = tid + k * 256;
             if (idx < HALO * V) {
                 const int pos = idx / V;
-                *reinterpret_cast<uint4*>(lds_in + pos * STRIDE + (idx - pos * V) * 8) = hv[k];
+                uint8_t* dst = lds_in + pos * STRIDE + (idx - pos * V) * 16;
+                if constexpr (F8) {   // 8-byte aligned positions
+                    reinterpret_cast<uint2*>(dst)[0] = make_uint2(hv[k].x, hv[k].y);
+                    reinterpret_cast<uint2*>(dst)[1] = make_uint2(hv[k].z, hv[k].w);
+                } else {
+                    *reinterpret_cast<uint4*>(dst) = hv[k];
+                }
             }
         }
         if (SYM) {
@@ -154,10 +197,10 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     // are read while this step's MFMAs run (the halo is not written in the loop,
     // so only the B slices need the per-tap barrier).  Fully unrolled so that the
     // fragment double buffer stays in registers.
-    uint4 afr[2][MB];
+    FragT afr[2][MB];
 #define WV_LOAD_A(dst, tp, ccv)                                                                      \
-    _Pragma("unroll") for (int mb_ = 0; mb_ < MB; ++mb_) dst[mb_] = *reinterpret_cast<const uint4*>( \
-        lds_in + ((row_of(mb_) + (tp) / 3) * HWD + m + (tp) % 3) * STRIDE + (ccv) * 32 + kk * 8);
+    _Pragma("unroll") for (int mb_ = 0; mb_ < MB; ++mb_) dst[mb_] = *reinterpret_cast<const FragT*>( \
+        lds_in + ((row_of(mb_) + (tp) / 3) * HWD + m + (tp) % 3) * STRIDE + ((ccv) * 32 + kk * 8) * ES);
     WV_LOAD_A(afr[0], 0, 0)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
@@ -165,11 +208,12 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         if (tap < 8) {
             WV_LOAD_B(tap + 1)
         }
-        uint4 bv[CC][NB];
+        const FragT* wb = reinterpret_cast<const FragT*>(lds_w[buf]);
+        FragT bv[CC][NB];
 #pragma unroll
         for (int cc = 0; cc < CC; ++cc)
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) bv[cc][nb] = lds_w[buf][(cc * NB + nb) * 64 + lane];
+            for (int nb = 0; nb < NB; ++nb) bv[cc][nb] = wb[(cc * NB + nb) * 64 + lane];
 #pragma unroll
         for (int cc = 0; cc < CC; ++cc) {
             const int st = tap * CC + cc;
@@ -181,9 +225,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(afr[st & 1][mb]), as_bf(bv[cc][nb]),
-                                                                          acc[mb][nb], 0, 0, 0);
+                for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_lp<F8>(afr[st & 1][mb], bv[cc][nb], acc[mb][nb]);
         }
         if (tap < 8) {
             WV_STORE_B(buf ^ 1)   // the other buffer was last read one tap ago
@@ -214,10 +256,13 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 
     const int col = lane & 15;
     const int rowq = (lane >> 4) * 4;
+    // FP8: the accumulator of packed column nc is scaled by L.scale[nc] before the bias.
+    float csc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) csc[nb] = F8 ? L.scale[(nblk0 + nb) * 16 + col] : 1.f;
     if constexpr (MODE == CONV_RELU || MODE == CONV_TANH) {
         // Stage the output tile [256 positions][16 NB channels] in LDS (reusing the
         // halo buffer), then write 16-byte chunks: full, coalesced lines.
-        constexpr int OS = NB * 16 + 8;
         static_assert(TH * TW * OS <= LDS_IN, "output tile does not fit the halo buffer");
         __syncthreads();
 #pragma unroll
@@ -227,22 +272,27 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                 const float b = L.bias[(nblk0 + nb) * 16 + col];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    float v = acc[mb][nb][i] + b;
+                    float v = F8 ? fmaf(acc[mb][nb][i], csc[nb], b) : acc[mb][nb][i] + b;
                     v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
-                    lds_in[(row_of(mb) * TW + rowq + i) * OS + nb * 16 + col] = f2bf(v);
+                    uint8_t* dst = lds_in + (row_of(mb) * TW + rowq + i) * OS + (nb * 16 + col) * ES;
+                    if constexpr (F8)
+                        *dst = f2e4m3(v);
+                    else
+                        *reinterpret_cast<uint16_t*>(dst) = f2bf(v);
                 }
             }
         __syncthreads();
-        constexpr int V8 = NB * 2;   // 16-byte chunks per position
-        for (int idx = tid; idx < TH * TW * V8; idx += 256) {
-            const int pos = idx / V8;
-            const int c8 = idx - pos * V8;
+        constexpr int V16 = NB * 16 * ES / 16;   // 16-byte chunks per position
+        uint8_t* outp = reinterpret_cast<uint8_t*>(a.out16);
+        for (int idx = tid; idx < TH * TW * V16; idx += 256) {
+            const int pos = idx / V16;
+            const int c16 = idx - pos * V16;
             const int r = r0 + pos / TW;
             const int c = c0 + pos % TW;
-            if (r < a.h && c < a.w && (nblk0 * 16 + c8 * 8) < L.cout)
-                *reinterpret_cast<uint4*>(a.out16 + (long long)n * a.out_ps +
-                                          ((long long)r * a.w + c) * a.out_cs + nblk0 * 16 + c8 * 8) =
-                    *reinterpret_cast<const uint4*>(lds_in + pos * OS + c8 * 8);
+            if (r < a.h && c < a.w && (nblk0 * 16 + c16 * 16 / ES) < L.cout)
+                *reinterpret_cast<uint4*>(outp + ((long long)n * a.out_ps +
+                                                  ((long long)r * a.w + c) * a.out_cs + nblk0 * 16) * ES +
+                                          c16 * 16) = *reinterpret_cast<const uint4*>(lds_in + pos * OS + c16 * 16);
         }
     } else if constexpr (MODE == CONV_LSTM) {
         const int ch = ycol * 16 + col;
@@ -262,15 +312,18 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                     if (a.c_prev)
                         cp = a.c_prev[(long long)n * a.cprev_ps +
                                       ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
-                    const float gi = sigmoidf_(acc[mb][0][i] + bi);
-                    const float gf = sigmoidf_(acc[mb][1][i] + bf);
-                    const float gg = tanhf(acc[mb][2][i] + bg);
-                    const float go = sigmoidf_(acc[mb][3][i] + bo);
+                    const float gi = sigmoidf_(fmaf(acc[mb][0][i], csc[0], bi));
+                    const float gf = sigmoidf_(fmaf(acc[mb][1][i], csc[1 % NB], bf));
+                    const float gg = tanhf(fmaf(acc[mb][2][i], csc[2 % NB], bg));
+                    const float go = sigmoidf_(fmaf(acc[mb][3][i], csc[3 % NB], bo));
                     const float cn = gf * cp + gi * gg;
                     const float hn = go * tanhf(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
                     a.c_out[o] = cn;
-                    a.h16_out[o] = f2bf(hn);
+                    if constexpr (F8)
+                        reinterpret_cast<uint8_t*>(a.h16_out)[o] = f2e4m3(hn);
+                    else
+                        a.h16_out[o] = f2bf(hn);
                 }
             }
         }
@@ -279,7 +332,8 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                lds_head[((wave * 2 + mb) * TW + rowq + i) * 17 + col] = acc[mb][0][i] + L.bias[col];
+                lds_head[((wave * 2 + mb) * TW + rowq + i) * 17 + col] =
+                    F8 ? fmaf(acc[mb][0][i], csc[0], L.bias[col]) : acc[mb][0][i] + L.bias[col];
         __syncthreads();
         if (tid < 8 * TW) {
             const int rr = tid / TW;                       // 0..7: wave rr/2, block rr%2
@@ -299,15 +353,16 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     }
 }
 
-template <int CIN, int NB, bool SYM, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16(const MfmaLayer16 L, const ConvArgs a) {
-    conv_tile_bf16<CIN, NB, SYM, MODE>(L, a, blockIdx.x, blockIdx.y);
+template <int CIN, int NB, bool SYM, int MODE, bool F8>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16(
+    const MfmaLayer16 L, const ConvArgs a) {
+    conv_tile_bf16<CIN, NB, SYM, MODE, F8>(L, a, blockIdx.x, blockIdx.y);
 }
 
 // Persistent multi-segment form (see the FP32 kernel).
-template <int CIN, int NB, bool SYM, int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16_seg(const ConvSeg16* __restrict__ segs, int nseg,
-                                                     long long total) {
+template <int CIN, int NB, bool SYM, int MODE, bool F8>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16_seg(
+    const ConvSeg16* __restrict__ segs, int nseg, long long total) {
     for (long long it = blockIdx.x; it < total; it += gridDim.x) {
         int lo = 0, hi = nseg;
         while (hi - lo > 1) {
@@ -317,36 +372,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         const ConvSeg16& S = segs[lo];
         const long long local = it - S.item0;
         const long long ntiles = (long long)S.a.tiles_x * S.a.tiles_y * S.a.N;
-        conv_tile_bf16<CIN, NB, SYM, MODE>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
+        conv_tile_bf16<CIN, NB, SYM, MODE, F8>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
         __syncthreads();
     }
 }
 
-template <int CIN, int NB, bool SYM, int MODE>
+template <int CIN, int NB, bool SYM, int MODE, bool F8>
 hipError_t launch_t(const MfmaLayer16& L, const ConvArgs& a0, hipStream_t s) {
     ConvArgs a = a0;
     a.tiles_x = (a.w + TW - 1) / TW;
     a.tiles_y = (a.h + TH - 1) / TH;
     const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
     dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
-    hipLaunchKernelGGL((conv3x3_mfma_bf16<CIN, NB, SYM, MODE>), grid, dim3(256), 0, s, L, a);
+    hipLaunchKernelGGL((conv3x3_mfma_bf16<CIN, NB, SYM, MODE, F8>), grid, dim3(256), 0, s, L, a);
     return hipGetLastError();
 }
 
-template <int CIN, int NB, bool SYM>
+template <int CIN, int NB, bool SYM, bool F8>
 hipError_t dispatch_mode(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
     switch (mode) {
-        case CONV_RELU: return launch_t<CIN, NB, SYM, CONV_RELU>(L, a, s);
-        case CONV_LSTM: return NB == 4 ? launch_t<CIN, 4, SYM, CONV_LSTM>(L, a, s) : hipErrorInvalidValue;
-        case CONV_HEAD: return NB == 1 ? launch_t<CIN, 1, SYM, CONV_HEAD>(L, a, s) : hipErrorInvalidValue;
+        case CONV_RELU: return launch_t<CIN, NB, SYM, CONV_RELU, F8>(L, a, s);
+        case CONV_LSTM: return NB == 4 ? launch_t<CIN, 4, SYM, CONV_LSTM, F8>(L, a, s) : hipErrorInvalidValue;
+        case CONV_HEAD: return NB == 1 ? launch_t<CIN, 1, SYM, CONV_HEAD, F8>(L, a, s) : hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
 
-template <int CIN, int NB>
+template <int CIN, int NB, bool F8>
 hipError_t dispatch_sym(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
-    return L.has_sym ? dispatch_mode<CIN, NB, true>(L, mode, a, s)
-                     : dispatch_mode<CIN, NB, false>(L, mode, a, s);
+    return L.has_sym ? dispatch_mode<CIN, NB, true, F8>(L, mode, a, s)
+                     : dispatch_mode<CIN, NB, false, F8>(L, mode, a, s);
 }
 
 inline int pick_nb(const MfmaLayer16& L, int mode, const ConvArgs& a) {
@@ -358,39 +413,41 @@ inline int pick_nb(const MfmaLayer16& L, int mode, const ConvArgs& a) {
     return nb;
 }
 
-template <int CIN>
+template <int CIN, bool F8>
 hipError_t dispatch_nb(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
     switch (pick_nb(L, mode, a)) {
-        case 1: return dispatch_sym<CIN, 1>(L, mode, a, s);
-        case 2: return dispatch_sym<CIN, 2>(L, mode, a, s);
-        case 4: return dispatch_sym<CIN, 4>(L, mode, a, s);
+        case 1: return dispatch_sym<CIN, 1, F8>(L, mode, a, s);
+        case 2: return dispatch_sym<CIN, 2, F8>(L, mode, a, s);
+        case 4: return dispatch_sym<CIN, 4, F8>(L, mode, a, s);
     }
     return hipErrorInvalidValue;
 }
 
-template <int CIN, int NB, bool SYM, int MODE>
+template <int CIN, int NB, bool SYM, int MODE, bool F8>
 hipError_t seg_t(const ConvSeg16* segs, int nseg, long long total, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((conv3x3_mfma_bf16_seg<CIN, NB, SYM, MODE>), dim3(grid), dim3(256), 0, s, segs, nseg,
+    hipLaunchKernelGGL((conv3x3_mfma_bf16_seg<CIN, NB, SYM, MODE, F8>), dim3(grid), dim3(256), 0, s, segs, nseg,
                        total);
     return hipGetLastError();
 }
 
-template <int CIN, int NB, bool SYM>
+template <int CIN, int NB, bool SYM, bool F8>
 hipError_t seg_mode(const ConvSeg16* segs, int nseg, long long total, int mode, int grid, hipStream_t s) {
     switch (mode) {
-        case CONV_RELU: return seg_t<CIN, NB, SYM, CONV_RELU>(segs, nseg, total, grid, s);
-        case CONV_LSTM: return NB == 4 ? seg_t<CIN, 4, SYM, CONV_LSTM>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
-        case CONV_HEAD: return NB == 1 ? seg_t<CIN, 1, SYM, CONV_HEAD>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+        case CONV_RELU: return seg_t<CIN, NB, SYM, CONV_RELU, F8>(segs, nseg, total, grid, s);
+        case CONV_LSTM:
+            return NB == 4 ? seg_t<CIN, 4, SYM, CONV_LSTM, F8>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
+        case CONV_HEAD:
+            return NB == 1 ? seg_t<CIN, 1, SYM, CONV_HEAD, F8>(segs, nseg, total, grid, s) : hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
 }
 
-template <int CIN>
+template <int CIN, bool F8>
 hipError_t seg_nb(const ConvSeg16* segs, int nseg, long long total, int sym, int mode, int nb, int grid,
                   hipStream_t s) {
-#define WV_SEG_NB(NBV)                                                                   \
-    if (nb == NBV) return sym ? seg_mode<CIN, NBV, true>(segs, nseg, total, mode, grid, s) \
-                              : seg_mode<CIN, NBV, false>(segs, nseg, total, mode, grid, s);
+#define WV_SEG_NB(NBV)                                                                         \
+    if (nb == NBV) return sym ? seg_mode<CIN, NBV, true, F8>(segs, nseg, total, mode, grid, s) \
+                              : seg_mode<CIN, NBV, false, F8>(segs, nseg, total, mode, grid, s);
     WV_SEG_NB(1) WV_SEG_NB(2) WV_SEG_NB(4)
 #undef WV_SEG_NB
     return hipErrorInvalidValue;
@@ -401,9 +458,14 @@ hipError_t seg_nb(const ConvSeg16* segs, int nseg, long long total, int sym, int
 hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total,
                                 const MfmaLayer16& proto, int mode, int nb, int grid, hipStream_t s) {
     if (total <= 0 || nseg <= 0) return hipSuccess;
+    const bool f8 = proto.scale != nullptr;
     switch (proto.cin) {
-        case 32: return seg_nb<32>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
-        case 64: return seg_nb<64>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
+        case 32:
+            return f8 ? seg_nb<32, true>(segs, nseg, total, proto.has_sym, mode, nb, grid, s)
+                      : seg_nb<32, false>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
+        case 64:
+            return f8 ? seg_nb<64, true>(segs, nseg, total, proto.has_sym, mode, nb, grid, s)
+                      : seg_nb<64, false>(segs, nseg, total, proto.has_sym, mode, nb, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -411,9 +473,10 @@ hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total
 hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s) {
     if (a.N <= 0 || a.h <= 0 || a.w <= 0) return hipSuccess;
     if (mode == CONV_LSTM && L.nbt % 4 != 0) return hipErrorInvalidValue;
+    const bool f8 = L.scale != nullptr;
     switch (L.cin) {
-        case 32: return dispatch_nb<32>(L, mode, a, s);
-        case 64: return dispatch_nb<64>(L, mode, a, s);
+        case 32: return f8 ? dispatch_nb<32, true>(L, mode, a, s) : dispatch_nb<32, false>(L, mode, a, s);
+        case 64: return f8 ? dispatch_nb<64, true>(L, mode, a, s) : dispatch_nb<64, false>(L, mode, a, s);
     }
     return hipErrorInvalidValue;
 }

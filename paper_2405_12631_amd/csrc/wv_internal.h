@@ -50,10 +50,15 @@ struct MfmaLayer {
 
 // BF16 variant: w [9][cin/32][nbt][64 lanes][8 bf16], wsym [nbt][64 lanes][8 bf16]
 // (element j of lane group kk is tap 8 kk + j), bias FP32 [nbt * 16].
+// Reduced-precision layer: BF16 weights (scale == nullptr), or FP8 e4m3 weights
+// with one FP32 scale per packed output column (the accumulator is multiplied by
+// it before the bias).  The symbol-channel weights are BF16 in both cases (for
+// FP8 already divided by the column's scale).
 struct MfmaLayer16 {
     const uint16_t* w;
     const uint16_t* wsym;
     const float* bias;
+    const float* scale;
     int cin, cout, nbt, has_sym;
 };
 
@@ -85,7 +90,8 @@ struct ConvArgs {
     float* c_out;
     long long st_ps;
     int C;
-    // BF16 kernels: activations / hidden state in BF16 (same strides, in elements)
+    // Reduced-precision kernels: activations / hidden state in BF16, or FP8 e4m3
+    // (one byte) when the layer has scales; same strides, in elements.
     const uint16_t* in16;
     uint16_t* out16;
     uint16_t* h16_out;
@@ -180,6 +186,9 @@ hipError_t launch_scatter(const uint8_t* sym, int16_t* q, int N, long long q_ps,
                           int h, int w, int step, int smin, hipStream_t s);
 hipError_t launch_gather(const int16_t* q, uint8_t* sym, int N, long long q_ps, long long off,
                          int h, int w, int step, int smin, hipStream_t s);
+size_t cdf_trim_scratch_bytes(long long n);
+hipError_t launch_cdf_trim(const uint16_t* cdf, long long n, int nsym, uint8_t* lolen, uint16_t* packed,
+                           long long* scratch, hipStream_t s);
 hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smin, int nsym,
                       uint16_t* cdf, hipStream_t s);
 hipError_t launch_thaar(float* f, float* tmp, int T, long long n, int inverse, hipStream_t s);

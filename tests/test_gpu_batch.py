@@ -15,14 +15,14 @@ def _images(sizes, seed=11):
     return [sinusoid_1f_planes(h, w, planes=3, seed=seed + k) for k, (h, w) in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_plan_params_equal_per_group_calls_bitwise(prec):
     need_gpu()
-    from paper_2405_12631_amd import codec, batch as B, WV_BF16, WV_FP32
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16, WV_FP32, WV_FP8
     say("plan vs per-group", prec)
     cfg = get_config("ycbcr512x768")
     model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)),
-                        precision=WV_BF16 if prec == "bf16" else WV_FP32)
+                        precision={"fp32": WV_FP32, "bf16": WV_BF16, "fp8": WV_FP8}[prec])
     imgs = _images(SIZES)
     bt = B.Batch(model, SIZES, nb_table=[1, 2, 4, 1])
     bt.load_images(imgs)

@@ -96,6 +96,42 @@ def test_cdf_extreme_params():
     assert empty.shape[0] == 0
 
 
+def test_cdf_trim_matches_oracle_definition():
+    need_gpu()
+    import ctypes
+    from paper_2405_12631_amd import codec, _lib as L
+    cfg = get_config("gray64")
+    model, _ = model_for(cfg)
+    rng = np.random.default_rng(43)
+    n = 300_000                                  # > 1024 blocks of 256 rows: several scan chunks
+    logits = rng.normal(0, 3, (n, 3))
+    w = np.exp(logits - logits.max(1, keepdims=True))
+    w /= w.sum(1, keepdims=True)
+    mu = rng.uniform(-90, 90, (n, 3))
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(100), (n, 3)))
+    prm = torch.from_numpy(np.concatenate([w, mu, sg], 1).astype(np.float32)).cuda()
+
+    class WS:                                    # trim buffers sized for n rows
+        pass
+    ws = WS()
+    tb = ctypes.c_size_t()
+    L.call("wv_cdf_trim_scratch_bytes", n, ctypes.byref(tb))
+    ws.lolen = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+    ws.packed = torch.empty(n * 128, dtype=torch.int16, device="cuda")
+    ws.trim_scratch = torch.empty(tb.value, dtype=torch.uint8, device="cuda")
+    for m in (1, 255, 256, 257, 5000, n):
+        say("cdf trim rows", m)
+        cdf = codec.cdf_tables(model, prm[:m])
+        full = cdf.cpu().numpy().view(np.uint16)
+        tr = codec.cdf_trim_to_host(model, cdf, ws)
+        k = min(m, 3000)                         # the oracle's definition, row by row, on a prefix
+        lolen, packed = O.cdf_trim(full[:k].astype(np.int64) + np.r_[np.zeros(129, np.int64), 65536])
+        assert np.array_equal(tr.lolen[:k], lolen)
+        assert np.array_equal(tr.packed[:tr.off[k]], packed)
+        assert np.array_equal(tr.full(), full)  # lossless at every size
+    assert codec.cdf_trim_to_host(model, codec.cdf_tables(model, prm[:0]), ws).lolen.shape == (0, 2)
+
+
 def test_encode_decode_roundtrip_bit_exact(small):
     say("roundtrip gray64")
     c = small["codec"]

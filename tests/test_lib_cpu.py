@@ -75,6 +75,15 @@ def test_shape_and_argument_errors():
     assert L.lib().wv_group_count(4, 4, 5) == -1
     nb = ctypes.c_size_t()
     assert L.lib().wv_pack_bytes(ctypes.byref(c), 9, ctypes.byref(nb)) == L.WV_EUNSUPPORTED
+    # Reduced precision packs the context convs smaller than FP32 (BF16: 2 bytes, FP8: 1 byte
+    # per weight plus per-channel scales) and needs the plain stacks.
+    sizes = {}
+    for prec in (L.WV_FP32, L.WV_BF16, L.WV_FP8):
+        assert L.lib().wv_pack_bytes(ctypes.byref(c), prec, ctypes.byref(nb)) == L.WV_OK
+        sizes[prec] = nb.value
+    assert sizes[L.WV_FP8] < sizes[L.WV_BF16] < sizes[L.WV_FP32]
+    blocks = codec.make_config(get_config("ycbcr512x768", ctx_arch="blocks"))
+    assert L.lib().wv_pack_bytes(ctypes.byref(blocks), L.WV_FP8, ctypes.byref(nb)) == L.WV_EUNSUPPORTED
     # GPU entry points reject bad arguments on the host before any launch.
     assert L.lib().wv_cdf_tables(None, 5, 3, 0, -64, 64, 16, None, None) == L.WV_EINVAL
     assert L.lib().wv_cdf_tables(None, 0, 3, 0, -64, 64, 12, None, None) == L.WV_EUNSUPPORTED
@@ -104,6 +113,30 @@ def test_host_rans_roundtrip_matches_reference_coder(cfg_small):
     back = codec.rans_decode(u16, data, len(idx), 129)
     assert np.array_equal(back, idx)
     assert 8 * len(data) <= O.ideal_bits(cdf, idx) * 1.002 + 64
+
+
+def test_host_trimmed_tables_and_coder(cfg_small):
+    _lib()
+    cdf, idx = _tables(33, 3000, cfg_small)
+    u16 = O.cdf_to_u16(cdf)
+    lolen, packed = O.cdf_trim(cdf)
+    tr = codec.Trimmed(lolen.astype(np.uint8), packed.astype(np.uint16), 129)
+    assert np.array_equal(tr.full(), u16)                      # library untrim == oracle tables
+    sym = idx.astype(np.uint8)
+    full = codec.rans_encode(u16, sym, 129)
+    for a, b in ((0, 3000), (0, 0), (1000, 2000), (2999, 3000)):
+        data = codec.rans_encode_trim(tr, a, b, sym[a:b])
+        assert data == codec.rans_encode(u16[a:b], sym[a:b], 129)
+        assert np.array_equal(codec.rans_decode_trim(tr, a, b, data), sym[a:b])
+    assert codec.rans_encode_trim(tr, 0, 3000, sym) == full
+    # (lo, len) that do not describe a row are refused
+    bad = lolen.astype(np.uint8).copy()
+    bad[17, 0] = 0
+    with pytest.raises(L.WvError) as e:
+        codec.Trimmed(bad, packed.astype(np.uint16), 129).full()
+    assert e.value.code == L.WV_ECORRUPT
+    with pytest.raises(L.WvError):
+        codec.rans_decode_trim(codec.Trimmed(bad, packed.astype(np.uint16), 129), 0, 3000, full)
 
 
 def test_host_rans_edge_cases(cfg_small):

@@ -173,3 +173,32 @@ def test_cdf_laplace_matches_high_precision_and_scipy(cfg_small):
     assert np.all(freq >= 1) and np.all(cdf[:, -1] == 65536) and np.all(cdf[:, 0] == 0)
     # The two families differ (a dropped family switch would pass the checks above).
     assert not np.array_equal(cdf, O.cdf_tables(p3, cfg_small))
+
+
+def test_cdf_trim_closed_form_single_gaussian(cfg_small):
+    # One N(mu, 1) component: F_j > 0 exactly where F_max Phi(b_j - mu) >= 1, and
+    # F_j < F_max - 1 exactly where F_max (1 - Phi(b_j - mu)) > 1, b_j = j - 64.5.
+    import scipy.stats
+    Fmax = 65536 - 129
+    zq = scipy.stats.norm.ppf(1.0 / Fmax)                     # about -4.17
+    for mu in (0.0, 10.25, -30.6):
+        cdf = O.cdf_tables(np.array([[1.0, mu, 1.0]]), dict(cfg_small, mix_k=1))
+        lolen, packed = O.cdf_trim(cdf)
+        lo = int(np.ceil(64.5 + mu + zq))
+        hi = int(np.ceil(64.5 + mu - zq)) - 1                  # last j with b_j - mu < -zq
+        assert tuple(lolen[0]) == (lo, hi - lo + 1)
+        assert np.array_equal(packed, cdf[0, lo:hi + 1] - np.arange(lo, hi + 1))
+
+
+def test_cdf_trim_roundtrip_and_size(cfg_small):
+    rng = np.random.default_rng(7)
+    n = 400
+    logits = rng.normal(0, 2, (n, 3))
+    w = np.exp(logits) / np.exp(logits).sum(1, keepdims=True)
+    mu = rng.uniform(-80, 80, (n, 3))                          # includes means beyond the alphabet
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(40), (n, 3)))
+    cdf = O.cdf_tables(np.concatenate([w, mu, sg], 1), cfg_small)
+    lolen, packed = O.cdf_trim(cdf)
+    assert np.array_equal(O.cdf_untrim(lolen, packed, 129), cdf)
+    assert lolen[:, 0].min() >= 1 and (lolen.sum(1) <= 129).all()
+    assert packed.size == lolen[:, 1].sum() < cdf[:, 1:129].size
