@@ -29,7 +29,6 @@ constexpr int HALO_H = TILE_H + 2;
 constexpr int HALO_W = TILE_W + 2;
 constexpr int HALO = HALO_H * HALO_W;
 
-__device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
 
 template <int CIN, int NB, bool SYM, int MODE, int TAPS>
 __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs& a, const int tile_idx,
@@ -236,7 +235,7 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[mb][nb][i] + b;
                     if (MODE == CONV_RELU) v = fmaxf(v, 0.f);
-                    if (MODE == CONV_TANH) v = tanhf(v);
+                    if (MODE == CONV_TANH) v = tanh_fast(v);
                     lds_in[((row0 + mb) * TILE_W + rowq + i) * OS + nb * 16 + col] = v;
                 }
             }
@@ -279,12 +278,12 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
                         cp = a.c_prev[(long long)n * a.cprev_ps +
                                       ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C +
                                       ch];
-                    const float gi = sigmoidf_(acc[mb][0][i] + bi);
-                    const float gf = sigmoidf_(acc[mb][1][i] + bf);
-                    const float gg = tanhf(acc[mb][2][i] + bg);
-                    const float go = sigmoidf_(acc[mb][3][i] + bo);
+                    const float gi = sigmoid_fast(acc[mb][0][i] + bi);
+                    const float gf = sigmoid_fast(acc[mb][1][i] + bf);
+                    const float gg = tanh_fast(acc[mb][2][i] + bg);
+                    const float go = sigmoid_fast(acc[mb][3][i] + bo);
                     const float cn = gf * cp + gi * gg;
-                    const float hn = go * tanhf(cn);
+                    const float hn = go * tanh_fast(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
                     a.c_out[o] = cn;
                     a.h_out[o] = hn;

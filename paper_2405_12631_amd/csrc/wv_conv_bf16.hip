@@ -33,7 +33,6 @@ constexpr int HH = TH + 2;
 constexpr int HWD = TW + 2;
 constexpr int HALO = HH * HWD;
 
-__device__ __forceinline__ float sigmoidf_(float v) { return 1.0f / (1.0f + __expf(-v)); }
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -273,7 +272,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = F8 ? fmaf(acc[mb][nb][i], csc[nb], b) : acc[mb][nb][i] + b;
-                    v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanhf(v);
+                    v = MODE == CONV_RELU ? fmaxf(v, 0.f) : tanh_fast(v);
                     uint8_t* dst = lds_in + (row_of(mb) * TW + rowq + i) * OS + (nb * 16 + col) * ES;
                     if constexpr (F8)
                         *dst = f2e4m3(v);
@@ -312,12 +311,12 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                     if (a.c_prev)
                         cp = a.c_prev[(long long)n * a.cprev_ps +
                                       ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
-                    const float gi = sigmoidf_(fmaf(acc[mb][0][i], csc[0], bi));
-                    const float gf = sigmoidf_(fmaf(acc[mb][1][i], csc[1 % NB], bf));
-                    const float gg = tanhf(fmaf(acc[mb][2][i], csc[2 % NB], bg));
-                    const float go = sigmoidf_(fmaf(acc[mb][3][i], csc[3 % NB], bo));
+                    const float gi = sigmoid_fast(fmaf(acc[mb][0][i], csc[0], bi));
+                    const float gf = sigmoid_fast(fmaf(acc[mb][1][i], csc[1 % NB], bf));
+                    const float gg = tanh_fast(fmaf(acc[mb][2][i], csc[2 % NB], bg));
+                    const float go = sigmoid_fast(fmaf(acc[mb][3][i], csc[3 % NB], bo));
                     const float cn = gf * cp + gi * gg;
-                    const float hn = go * tanhf(cn);
+                    const float hn = go * tanh_fast(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
                     a.c_out[o] = cn;
                     if constexpr (F8)

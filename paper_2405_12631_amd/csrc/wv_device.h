@@ -10,6 +10,15 @@
 
 namespace wv {
 
+// tanh x = 1 - 2 / (e^{2x} + 1) and the logistic 1 / (1 + e^{-x}) from the
+// hardware exponential and reciprocal: absolute error about 1e-7, the exact
+// limits for large |x| (e^{2x} overflowing to inf gives 1, underflowing to 0
+// gives -1).
+__device__ __forceinline__ float tanh_fast(float x) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * x));
+}
+__device__ __forceinline__ float sigmoid_fast(float x) { return __builtin_amdgcn_rcpf(1.0f + __expf(-x)); }
+
 // Mixture head (Sec. 3.1 / 3.2 entropy parameters): raw 3K values ->
 // w = softmax(v[0:K]), mu = v[K:2K], sigma = max(softplus(v[2K:3K]), sigma_min).
 __device__ __forceinline__ void mixture_head(const float* v, int K, float sigma_min, float* o) {

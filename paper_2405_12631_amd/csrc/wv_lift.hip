@@ -7,6 +7,7 @@
 // applies the lifting update in place of a separate pass:
 //   predict: f = z + N(z); update: f = z/2 + N(z); optionally rounded;
 //   out = A + sign * f.
+#include "wv_device.h"
 #include "wv_internal.h"
 
 namespace wv {
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(BLK) void lift_first_k(const VecLayer L, const CVie
             float s = L.bias[ch + j];
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) s = fmaf(L.w[tap * C + ch + j], zv[tap], s);
-            v[j] = tanhf(s);
+            v[j] = tanh_fast(s);
         }
         *reinterpret_cast<float4*>(o + ch) = make_float4(v[0], v[1], v[2], v[3]);
     }

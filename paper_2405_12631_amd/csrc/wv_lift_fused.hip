@@ -8,6 +8,7 @@
 // overwrites the first layer's buffer), the last layer and the update on the
 // 8 x 16 outputs.  Positions outside the array are zero in every layer, which
 // is exactly the per-layer zero padding of the definition.
+#include "wv_device.h"
 #include "wv_internal.h"
 
 namespace wv {
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
 #pragma unroll
                 for (int tap = 0; tap < 9; ++tap) s[j] = fmaf(w1s[tap * C + c4 + j], zv[tap], s[j]);
             }
-            v = make_float4(tanhf(s[0]), tanhf(s[1]), tanhf(s[2]), tanhf(s[3]));
+            v = make_float4(tanh_fast(s[0]), tanh_fast(s[1]), tanh_fast(s[2]), tanh_fast(s[3]));
         }
         *reinterpret_cast<float4*>(act + pos * S1 + c4) = v;
     }
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
                 if (p >= NP2) continue;
                 const int r = r0 - 1 + p / BW, c = c0 - 1 + p % BW;
                 const bool in = r >= 0 && r < h && c >= 0 && c < w;
-                act[p * S1 + ch] = in ? tanhf(acc[j][nb][i] + b2s[ch]) : 0.f;
+                act[p * S1 + ch] = in ? tanh_fast(acc[j][nb][i] + b2s[ch]) : 0.f;
             }
         }
     }
