@@ -31,6 +31,32 @@ sys.path.insert(0, ROOT)
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
 
 
+# HBM bytes per context-conv launch from rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0), the
+# factors being what each counter reads for a plain 1 GiB device copy; averaged over the 663
+# launches of three 512x768x3 decodes.  Valid only for the conv sources with these sha256.
+TRAFFIC_SOURCES = {
+    "paper_2405_12631_amd/csrc/wv_conv.hip": "0c75c2738701b7f58744f114f4430a55fd404187836450b942d3b72b722c31dd",
+    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "88ef0b73956dab517ad50582f70079d856d5d8fe914a1fe7a6caa12d2bb83acf",
+    "paper_2405_12631_amd/csrc/wv_device.h": "b20ce3ff0225e18b14ad70a1560cf9a9bcc2c4b28cfb200f15dd07098e331a8e",
+    "paper_2405_12631_amd/csrc/wv_internal.h": "ceef266fead583a11cee5c5340318c9938bc13b002a260937f5688aa65621e92",
+}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 53.94e6, "bf16": 28.57e6, "fp8": 17.21e6}
+
+
+def measured_traffic(precision):
+    """Counter-measured HBM bytes per context-conv launch, or None if the kernels changed since."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel, digest in TRAFFIC_SOURCES.items():
+        try:
+            with open(os.path.join(root, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
+        except OSError:
+            return None
+    return TRAFFIC_BYTES_PER_LAUNCH.get(precision)
+
+
 def _precision(name):
     from paper_2405_12631_amd import WV_BF16, WV_FP32, WV_FP8
     return {"fp32": WV_FP32, "bf16": WV_BF16, "fp8": WV_FP8}[name]
@@ -295,6 +321,54 @@ def precision_report(args):
     print(json.dumps(out))
 
 
+def bench_coder(args):
+    """End-to-end decode of the 512x768x3 image through the host entropy coder: for every
+    step the CDF rows are trimmed on the device, copied to the host (PCIe), the host rANS
+    decoder runs per plane, the symbols go back and are scattered; then synthesis.  Reports
+    the PCIe-inclusive rate and the bytes copied per decode with and without the trim."""
+    import torch
+    from paper_2405_12631_amd import codec
+    from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes
+
+    cfg = get_config("ycbcr512x768")
+    H, W, N = cfg["H"], cfg["W"], cfg["planes"]
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=_precision(args.precision))
+    x = sinusoid_1f_planes(H, W, planes=N, seed=cfg["seed_image"])
+    data, q_enc = codec.encode(model, x)
+    ws = codec.Workspace(model, N, H, W)
+    for _ in range(args.warmup):
+        codec.decode(model, data, ws=ws)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        _, _, q_dec = codec.decode(model, data, ws=ws)
+        torch.cuda.synchronize()
+        t.append(time.perf_counter() - t0)
+    assert torch.equal(q_dec, q_enc), "host-coder decode did not reproduce the symbols"
+    # bytes a decode copies device -> host for the tables: trimmed vs full rows
+    full = trimmed = 0
+    for i in range(len(ws.lay)):
+        for g in range(4):
+            prm = codec.context_params(model, q_enc, ws, i, g)
+            cdf = codec.cdf_tables(model, prm, out=ws.cdf)
+            tr = codec.cdf_trim_to_host(model, cdf, ws)
+            full += cdf.numel() * 2
+            trimmed += tr.lolen.nbytes + tr.packed.nbytes
+    t = np.array(t)
+    out = dict(
+        metric="decoded Mpixel/s end to end with the host entropy coder (PCIe-inclusive)",
+        value=round(H * W / t.mean() / 1e6, 4), unit="Mpixel/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(t.mean() * 1e3, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=args.precision, data="synthetic",
+        config=dict(workload="ycbcr512x768 through the host rANS decoder: 52 table copies (trimmed) and "
+                             "symbol copies per plane group, coder on host threads", bytes=len(data)),
+        p50_ms=round(float(np.percentile(t, 50)) * 1e3, 3), p99_ms=round(float(np.percentile(t, 99)) * 1e3, 3),
+        table_bytes_to_host=dict(full=full, trimmed=trimmed, ratio=round(full / max(trimmed, 1), 2)),
+    )
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,7 +379,7 @@ def main():
                     help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
                          "bf16 for the batched and serving workloads")
     ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix",
-                                           "precision_report"],
+                                           "precision_report", "coder512x768"],
                     default="ycbcr512x768")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=20.0, help="time allowed to drain after it")
@@ -321,6 +395,9 @@ def main():
         return bench_batch(args)
     if args.workload == "precision_report":
         return precision_report(args)
+    if args.workload == "coder512x768":
+        args.precision = args.precision or "fp32"
+        return bench_coder(args)
     if args.workload == "serve_mix":
         args.precision = args.precision or "bf16"
         return bench_serve(args)
@@ -400,7 +477,8 @@ def main():
              "fp8": "conv3x3_mfma_bf16 (e4m3 form)"}[args.precision]
     roof = dict(bound="mfma", achieved=round(ctx_flops / ctx_time / 1e12, 3),
                 peak=peak, unit="TFLOP/s",
-                frac=round(ctx_flops / ctx_time / 1e12 / peak, 4), traffic=None,
+                frac=round(ctx_flops / ctx_time / 1e12 / peak, 4), traffic=measured_traffic(args.precision),
+                traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 kernel=f"{kname} (context model: ConvLSTM + step stacks)",
                 flops_per_decode=ctx_flops, launches_per_decode=n_ctx_launch,
                 avg_launch_us=round(ctx_time / n_ctx_launch * 1e6, 2))
