@@ -1291,7 +1291,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                     const Sub& S = P->lay[b][i];
                     tiles += (long long)((S.w + tw - 1) / tw) * ((S.h + th - 1) / th) * groups[b].nplanes;
                 }
-                int nb = conv_pick_nb(nbt, mode, tiles);
+                int nb = conv_pick_nb(nbt, mode, tiles, bf16);
                 if (nb_table && mode == CONV_RELU) {
                     const int want = nb_table[level - 1];
                     if (want == 1 || want == 2 || want == 4) nb = want <= nbt ? want : nbt;
@@ -1514,7 +1514,7 @@ void item_seg(ItemLaunch& Lc, bool bf16, const MfmaLayer* L32, const MfmaLayer16
 void item_finish(ItemLaunch& Lc, bool bf16) {
     if (!Lc.nseg) return;
     const int nbt = bf16 ? Lc.proto16.nbt : Lc.proto.nbt;
-    Lc.nb = conv_pick_nb(nbt, Lc.mode, Lc.tiles);
+    Lc.nb = conv_pick_nb(nbt, Lc.mode, Lc.tiles, bf16);
     long long item = 0;
     const size_t ss = bf16 ? sizeof(ConvSeg16) : sizeof(ConvSeg);
     for (int k = 0; k < Lc.nseg; ++k) {

@@ -377,12 +377,7 @@ hipError_t dispatch_sym(const MfmaLayer& L, int mode, int taps, const ConvArgs& 
 // the output channels are spread over more workgroups (each output's
 // accumulation order is unchanged, so the bits are too).
 inline int pick_nb(const MfmaLayer& L, int mode, const ConvArgs& a) {
-    if (mode == CONV_HEAD) return 1;
-    if (mode == CONV_LSTM) return 4;
-    const long long tiles = (long long)a.tiles_x * a.tiles_y * a.N;
-    int nb = L.nbt >= 4 ? 4 : L.nbt;
-    while (nb > 1 && tiles * (L.nbt / nb) < 512) nb >>= 1;
-    return nb;
+    return conv_pick_nb(L.nbt, mode, (long long)a.tiles_x * a.tiles_y * a.N, 0);
 }
 
 template <int CIN>
@@ -436,12 +431,18 @@ hipError_t seg_nb(const ConvSeg* segs, int nseg, long long total, int sym, int m
 
 }  // namespace
 
-int conv_pick_nb(int nbt, int mode, long long tiles) {
+// Output-channel blocks per workgroup.  Four blocks reuse each A fragment most
+// and win when the tiles fill the device for two or more rounds of resident
+// workgroups (2 per CU); with fewer tiles, narrower blocks give more, shorter
+// workgroups and a smaller last round (measured per level on the 512x768 image:
+// FP32 best at one block, BF16/FP8 at two).  The choice never changes results.
+int conv_pick_nb(int nbt, int mode, long long tiles, int lowp) {
     if (mode == CONV_HEAD) return 1;
     if (mode == CONV_LSTM) return 4;
-    int nb = nbt >= 4 ? 4 : nbt;
-    while (nb > 1 && tiles * (nbt / nb) < 512) nb >>= 1;
-    return nb;
+    const int widest = nbt >= 4 ? 4 : nbt;
+    if (tiles >= 1024) return widest;
+    const int narrow = lowp ? 2 : 1;
+    return narrow < widest ? narrow : widest;
 }
 int conv_tile_h(int bf16) { return bf16 ? 16 : TILE_H; }
 int conv_tile_w(int bf16) { return bf16 ? 16 : TILE_W; }

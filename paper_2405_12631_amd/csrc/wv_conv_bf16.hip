@@ -404,12 +404,7 @@ hipError_t dispatch_sym(const MfmaLayer16& L, int mode, const ConvArgs& a, hipSt
 }
 
 inline int pick_nb(const MfmaLayer16& L, int mode, const ConvArgs& a) {
-    if (mode == CONV_HEAD) return 1;
-    if (mode == CONV_LSTM) return 4;
-    const long long tiles = (long long)((a.w + TW - 1) / TW) * ((a.h + TH - 1) / TH) * a.N;
-    int nb = L.nbt >= 4 ? 4 : L.nbt;
-    while (nb > 1 && tiles * (L.nbt / nb) < 512) nb >>= 1;
-    return nb;
+    return conv_pick_nb(L.nbt, mode, (long long)((a.w + TW - 1) / TW) * ((a.h + TH - 1) / TH) * a.N, 1);
 }
 
 template <int CIN, bool F8>

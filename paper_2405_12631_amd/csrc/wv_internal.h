@@ -124,7 +124,7 @@ hipError_t launch_conv_seg(const ConvSeg* segs, int nseg, long long total, const
 hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total,
                                 const MfmaLayer16& proto, int mode, int nb, int grid, hipStream_t s);
 // Output blocks per workgroup chosen for a launch of `tiles` position tiles.
-int conv_pick_nb(int nbt, int mode, long long tiles);
+int conv_pick_nb(int nbt, int mode, long long tiles, int lowp);
 int conv_tile_h(int bf16);
 int conv_tile_w(int bf16);
 
