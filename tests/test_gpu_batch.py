@@ -95,3 +95,40 @@ def test_batch_result_equals_single_image_decode():
         alone = codec.decode_elided(model, syms, ws, q0)
         gb, p0 = bt.where[k]
         assert torch.equal(alone, out[gb][p0:p0 + 3]), k
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_single_image_graph_replays_equal_eager(prec):
+    # The bench times replays of one captured single-image decode; every replay, with eager
+    # work and synchronisations in between, must equal the eager decode bit for bit.
+    need_gpu()
+    from paper_2405_12631_amd import codec, WV_BF16, WV_FP32
+    say("single-image graph", prec)
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)),
+                        precision=WV_BF16 if prec == "bf16" else WV_FP32)
+    x = sinusoid_1f_planes(64, 96, planes=3, seed=5)
+    ws = codec.Workspace(model, 3, 64, 96)
+    q_known, _, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws)
+    syms = codec.prepare_elided(model, q_known, ws)
+    q = torch.zeros_like(q_known)
+    xhat = torch.empty((3, 64, 96), dtype=torch.float32, device="cuda")
+
+    def step():
+        q.zero_()
+        codec.decode_elided(model, syms, ws, q, xhat)
+
+    step()
+    torch.cuda.synchronize()
+    ref_q, ref_x = q.clone(), xhat.clone()
+    assert torch.equal(ref_q, q_known)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for _ in range(3):
+        q.fill_(7)
+        xhat.fill_(-1.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(q, ref_q) and torch.equal(xhat, ref_x)

@@ -31,14 +31,14 @@ def _alone(model, prep):
     return outs
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
 def test_served_results_equal_alone_results(prec):
     need_gpu()
-    from paper_2405_12631_amd import codec, serve, WV_BF16, WV_FP32
+    from paper_2405_12631_amd import codec, serve, WV_BF16, WV_FP32, WV_FP8
     say("serve mix", prec)
     cfg = get_config("ycbcr512x768")
     model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)),
-                        precision=WV_BF16 if prec == "bf16" else WV_FP32)
+                        precision={"fp32": WV_FP32, "bf16": WV_BF16, "fp8": WV_FP8}[prec])
     luma, chroma = video_gop_420(T=8, H=64, W=64, seed=5)
     preps = {0: serve.Prepared(model, "image", sinusoid_1f_planes(64, 96, 3, seed=1)),
              1: serve.Prepared(model, "image", sinusoid_1f_planes(32, 48, 3, seed=2)),
