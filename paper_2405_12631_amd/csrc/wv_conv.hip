@@ -5,8 +5,8 @@
 // layers of the lifting filters (Sec. 3.1).
 //
 // GEMM view: M = output positions, N = output channels, K = 9 taps x Cin.
-// One workgroup (256 threads, 4 waves) owns an 8 x 16 position tile and
-// 16*NB output channels.  The (8+2) x (16+2) input halo of all Cin channels
+// One workgroup (256 threads, 4 waves) works on an 8 x 16 position tile and
+// 16*NB output channels at a time, walking its share of the tiles.  The (8+2) x (16+2) input halo of all Cin channels
 // is staged once in LDS (NHWC, row stride Cin+4 floats); each wave computes
 // two rows of 16 positions x NB blocks of 16 channels with
 // v_mfma_f32_16x16x4f32, A fragments read from LDS as float4 (4 channels of
@@ -29,16 +29,45 @@ constexpr int HALO_H = TILE_H + 2;
 constexpr int HALO_W = TILE_W + 2;
 constexpr int HALO = HALO_H * HALO_W;
 
+// Persistent form for every launch: a workgroup walks items it = blockIdx.x,
+// + gridDim.x, ... (item = (tile, column of NB 16-channel blocks) of one segment =
+// one layer over one group of planes; a single-layer launch is one segment).
+// The next item's halo is loaded into registers a slice per tap while this
+// item's MFMAs run, next to that tap's weight load (so waiting for the weights
+// never waits for a halo load issued later); at the last tap the next item's
+// first weight slice and symbol inputs follow.  Static assignment, same bits.
+struct ItemPosF {
+    int n, r0, c0, ycol;
+};
 
-template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs& a, const int tile_idx,
-                                              const int ycol) {
+__device__ __forceinline__ ItemPosF item_pos_f32(const ConvArgs& a, long long local) {
+    const long long ntiles = (long long)a.tiles_x * a.tiles_y * a.N;
+    int t = (int)(local % ntiles);
+    ItemPosF p;
+    p.ycol = (int)(local / ntiles);
+    const int tx = t % a.tiles_x;
+    t /= a.tiles_x;
+    const int ty = t % a.tiles_y;
+    p.n = t / a.tiles_y;
+    p.r0 = ty * TILE_H;
+    p.c0 = tx * TILE_W;
+    return p;
+}
+
+template <int CIN, int NB, bool SYM, int MODE, int TAPS, bool MULTI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_f32p(
+    const ConvSeg* __restrict__ segs, int nseg, const ConvSeg one, long long total) {
     // TAPS == 9: 3x3 conv; TAPS == 1: 1x1 conv (centre tap only, same data path).
     constexpr int STRIDE = CIN + 4;          // 68 floats for CIN = 64: conflict-free float4 reads
     constexpr int CB = CIN / 16;
     constexpr int BV4 = CB * NB * 64;        // float4 of B per tap for this workgroup's N blocks
     constexpr int BPT = (BV4 + 255) / 256;   // float4 per thread
     constexpr int MB = (MODE == CONV_HEAD) ? 1 : 2;   // head: only the row parity its step codes
+    constexpr int V = CIN / 4;               // float4 per halo position
+    constexpr int NH = (HALO * V + 255) / 256;
+    constexpr int NS = (HALO + 255) / 256;
+    constexpr int NWS = (3 * NB * 64 + 255) / 256;
+    static_assert(BPT <= 4, "B slice larger than four float4 per thread");
     // Input halo; after the MFMA loop it holds the output tile (RELU/TANH epilogue).
     constexpr int LDS_IN = HALO * STRIDE > TILE_H * TILE_W * (NB * 16 + 4) ? HALO * STRIDE
                                                                             : TILE_H * TILE_W * (NB * 16 + 4);
@@ -48,43 +77,44 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
     __shared__ float lds_ws[SYM ? 3 * NB * 64 : 1];
     __shared__ float lds_head[MODE == CONV_HEAD ? 4 * TILE_W * 17 : 1];
 
+    long long it = blockIdx.x;
+    if (it >= total) return;
+    auto seg_index = [&](long long i) -> int {
+        if constexpr (!MULTI) {
+            return 0;
+        } else {
+            int lo = 0, hi = nseg;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (segs[mid].item0 <= i) lo = mid; else hi = mid;
+            }
+            return lo;
+        }
+    };
+#define WV_SEG(i) (MULTI ? segs[i] : one)
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int t = tile_idx;
-    const int tx = t % a.tiles_x;
-    t /= a.tiles_x;
-    const int ty = t % a.tiles_y;
-    const int n = t / a.tiles_y;
-    const int r0 = ty * TILE_H;
-    const int c0 = tx * TILE_W;
-    const int nblk0 = ycol * NB;
-    const int row0 = wave * 2 + (MODE == CONV_HEAD ? (a.step >> 1) : 0);   // first tile row of this wave
+    const int m = lane & 15;
+    const int kk = lane >> 4;
 
-    // B fragments of one tap for blocks [nblk0, nblk0 + NB): global [tap][cb][nbt][64][4].
-    // Thread tid moves float4 number tid + 256 k (k < BPT <= 4) of the slice, whose
-    // layout in LDS is [cb][nb][64 lanes].  Named registers keep the prefetch out of memory.
-    static_assert(BPT <= 4, "B slice larger than four float4 per thread");
-    const float4* wg = reinterpret_cast<const float4*>(L.w);
-    auto boff_of = [&](int k) -> long long {
-        const int idx = (tid + k * 256) < BV4 ? tid + k * 256 : 0;
-        const int cb = idx / (NB * 64);
-        const int rem = idx - cb * (NB * 64);
-        return ((long long)cb * L.nbt + nblk0 + (rem >> 6)) * 64 + (rem & 63);
-    };
-    const long long bo0 = boff_of(0);
-    const long long bo1 = BPT > 1 ? boff_of(1) : 0;
-    const long long bo2 = BPT > 2 ? boff_of(2) : 0;
-    const long long bo3 = BPT > 3 ? boff_of(3) : 0;
-    const long long btap = (long long)CB * L.nbt * 64;   // float4 per tap of the whole layer
-    float4 b0, b1, b2, b3;
-#define WV_LOAD_B(tp)                                          \
-    {                                                          \
-        const float4* wt_ = wg + (long long)(tp) * btap;       \
-        b0 = wt_[bo0];                                         \
-        if (BPT > 1) b1 = wt_[bo1];                            \
-        if (BPT > 2) b2 = wt_[bo2];                            \
-        if (BPT > 3) b3 = wt_[bo3];                            \
+    float4 hv[NH];
+    float sv[NS];
+    float wsv[NWS];
+    float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0, b3 = b0;
+    // B fragments of tap tp for blocks [ycq NB, ycq NB + NB): global [tap][cb][nbt][64][4], LDS [cb][nb][64].
+#define WV_LOAD_B(Lq, ycq, tp)                                                                     \
+    {                                                                                              \
+        const float4* wt_ = reinterpret_cast<const float4*>((Lq).w) + (long long)(tp) * CB * (Lq).nbt * 64; \
+        _Pragma("unroll") for (int k_ = 0; k_ < BPT; ++k_) {                                       \
+            const int idx_ = tid + k_ * 256;                                                       \
+            if (idx_ < BV4) {                                                                      \
+                const int cb_ = idx_ / (NB * 64);                                                  \
+                const int rem_ = idx_ - cb_ * (NB * 64);                                           \
+                const float4 v_ = wt_[((long long)cb_ * (Lq).nbt + (ycq) * NB + (rem_ >> 6)) * 64 + (rem_ & 63)]; \
+                if (k_ == 0) b0 = v_; else if (k_ == 1) b1 = v_; else if (k_ == 2) b2 = v_; else b3 = v_; \
+            }                                                                                      \
+        }                                                                                          \
     }
 #define WV_STORE_B()                                                       \
     {                                                                      \
@@ -93,28 +123,66 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
         if (BPT > 2 && (BV4 >= 768 || tid + 512 < BV4)) lds_w[tid + 512] = b2; \
         if (BPT > 3 && (BV4 >= 1024 || tid + 768 < BV4)) lds_w[tid + 768] = b3; \
     }
-    WV_LOAD_B(0)
+#define WV_LOAD_H(A, P, k)                                                                         \
+    {                                                                                              \
+        const int idx_ = tid + (k) * 256;                                                          \
+        const int pos_ = idx_ / V;                                                                 \
+        const int c4_ = idx_ - pos_ * V;                                                           \
+        const int hy_ = pos_ / HALO_W;                                                             \
+        const int r_ = (P).r0 + hy_ - 1;                                                           \
+        const int c_ = (P).c0 + (pos_ - hy_ * HALO_W) - 1;                                         \
+        hv[k] = make_float4(0.f, 0.f, 0.f, 0.f);                                                   \
+        if (idx_ < HALO * V && (A).in && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w)            \
+            hv[k] = *reinterpret_cast<const float4*>(                                              \
+                (A).in + (long long)(P).n * (A).in_ps +                                            \
+                ((long long)(r_ >> (A).in_up) * ((A).w >> (A).in_up) + (c_ >> (A).in_up)) * CIN + c4_ * 4); \
+    }
+#define WV_LOAD_S(A, Lq, P)                                                                        \
+    if constexpr (SYM) {                                                                           \
+        const int16_t* sp_ = (A).sym ? (A).sym + (long long)(P).n * (A).sym_ps : nullptr;           \
+        const int ws_ = (A).w >> (A).sym_up;                                                       \
+        _Pragma("unroll") for (int k_ = 0; k_ < NS; ++k_) {                                        \
+            const int pos_ = tid + k_ * 256;                                                       \
+            const int hy_ = pos_ / HALO_W;                                                         \
+            const int r_ = (P).r0 + hy_ - 1;                                                       \
+            const int c_ = (P).c0 + (pos_ - hy_ * HALO_W) - 1;                                     \
+            float v_ = 0.f;                                                                        \
+            if (pos_ < HALO && sp_ && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w &&             \
+                (2 * (r_ & 1) + (c_ & 1)) < (A).sym_step)                                          \
+                v_ = (float)sp_[(long long)(r_ >> (A).sym_up) * ws_ + (c_ >> (A).sym_up)];          \
+            sv[k_] = v_;                                                                           \
+        }                                                                                          \
+        _Pragma("unroll") for (int k_ = 0; k_ < NWS; ++k_) {                                       \
+            const int idx_ = tid + k_ * 256;                                                       \
+            wsv[k_] = 0.f;                                                                         \
+            if (idx_ < 3 * NB * 64) {                                                              \
+                const int chunk_ = idx_ / (NB * 64);                                               \
+                const int rem_ = idx_ - chunk_ * (NB * 64);                                        \
+                wsv[k_] = (Lq).wsym[((long long)chunk_ * (Lq).nbt + (P).ycol * NB) * 64 + rem_];   \
+            }                                                                                      \
+        }                                                                                          \
+    }
 
-    // ---- stage the input halo (zero outside the plane) ----
+    int si = seg_index(it);
     {
-        const int win = a.w >> a.in_up;
-        const float* inp = a.in ? a.in + (long long)n * a.in_ps : nullptr;
-        constexpr int V = CIN / 4;                   // float4 per position
-        constexpr int NH = (HALO * V + 255) / 256;   // per thread: all loads in flight before any store
-        float4 hv[NH];
+        const ConvSeg& S0 = WV_SEG(si);
+        const ItemPosF P0 = item_pos_f32(S0.a, it - S0.item0);
 #pragma unroll
-        for (int k = 0; k < NH; ++k) {
-            const int idx = tid + k * 256;
-            const int pos = idx / V;
-            const int c4 = idx - pos * V;
-            const int hy = pos / HALO_W;
-            const int r = r0 + hy - 1;
-            const int c = c0 + (pos - hy * HALO_W) - 1;
-            hv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (idx < HALO * V && inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
-                hv[k] = *reinterpret_cast<const float4*>(
-                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN + c4 * 4);
-        }
+        for (int k = 0; k < NH; ++k) WV_LOAD_H(S0.a, P0, k)
+        WV_LOAD_S(S0.a, S0.L, P0)
+        WV_LOAD_B(S0.L, P0.ycol, 0)
+    }
+
+    for (; it < total; it += gridDim.x) {
+        const ConvSeg& S = WV_SEG(si);
+        const MfmaLayer& L = S.L;
+        const ConvArgs& a = S.a;
+        const ItemPosF P = item_pos_f32(a, it - S.item0);
+        const int n = P.n, r0 = P.r0, c0 = P.c0, ycol = P.ycol;
+        const int nblk0 = ycol * NB;
+        const int row0 = wave * 2 + (MODE == CONV_HEAD ? (a.step >> 1) : 0);   // first tile row of this wave
+
+        __syncthreads();   // the previous item is done with every LDS buffer
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
             const int idx = tid + k * 256;
@@ -123,75 +191,69 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
                 *reinterpret_cast<float4*>(lds_in + pos * STRIDE + (idx - pos * V) * 4) = hv[k];
             }
         }
-        if (SYM) {
-            const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
-            const int ws = a.w >> a.sym_up;
-            for (int pos = tid; pos < HALO; pos += 256) {
-                const int hy = pos / HALO_W;
-                const int hx = pos - hy * HALO_W;
-                const int r = r0 + hy - 1;
-                const int c = c0 + hx - 1;
-                float v = 0.f;
-                if (sp && r >= 0 && r < a.h && c >= 0 && c < a.w &&
-                    (2 * (r & 1) + (c & 1)) < a.sym_step)
-                    v = (float)sp[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
-                lds_s[pos] = v;
+        if constexpr (SYM) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                if (tid + k * 256 < HALO) lds_s[tid + k * 256] = sv[k];
+#pragma unroll
+            for (int k = 0; k < NWS; ++k)
+                if (tid + k * 256 < 3 * NB * 64) lds_ws[tid + k * 256] = wsv[k];
+        }
+        WV_STORE_B()
+        __syncthreads();
+
+        const long long nx = it + gridDim.x;
+        const bool has_next = nx < total;
+        const int sn = has_next ? seg_index(nx) : si;
+        const ConvSeg& SN = WV_SEG(sn);
+        const ItemPosF PN = item_pos_f32(SN.a, nx - SN.item0);
+
+        floatx4 acc[MB][NB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+        for (int tap = 0; tap < TAPS; ++tap) {
+            if (tap < TAPS - 1) {
+                WV_LOAD_B(L, ycol, tap + 1)   // in flight while this tap computes
+            } else if (has_next) {
+                WV_LOAD_B(SN.L, PN.ycol, 0)
+                WV_LOAD_S(SN.a, SN.L, PN)
             }
-            for (int idx = tid; idx < 3 * NB * 64; idx += 256) {
-                const int chunk = idx / (NB * 64);
-                const int rem = idx - chunk * (NB * 64);
-                lds_ws[idx] = L.wsym[((long long)chunk * L.nbt + nblk0) * 64 + rem];
+            if (has_next) {   // this tap's share of the next item's halo
+#pragma unroll
+                for (int k = tap * NH / TAPS; k < (tap + 1) * NH / TAPS; ++k) WV_LOAD_H(SN.a, PN, k)
+            }
+            const int dy = TAPS == 1 ? 1 : tap / 3;
+            const int dx = TAPS == 1 ? 1 : tap - dy * 3;
+            const float* arow0 = lds_in + ((row0 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                float4 av[MB];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    av[mb] = *reinterpret_cast<const float4*>(arow0 + mb * HALO_W * STRIDE + cb * 16);
+                float4 bv[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) bv[nb] = lds_w[(cb * NB + nb) * 64 + lane];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].x, bv[nb].x, acc[mb][nb], 0, 0, 0);
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].y, bv[nb].y, acc[mb][nb], 0, 0, 0);
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].z, bv[nb].z, acc[mb][nb], 0, 0, 0);
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].w, bv[nb].w, acc[mb][nb], 0, 0, 0);
+                    }
+            }
+            if (tap < TAPS - 1) {
+                __syncthreads();   // every wave is done with this tap's B
+                WV_STORE_B()
+                __syncthreads();
             }
         }
-    }
-    WV_STORE_B()
-    __syncthreads();
-
-    floatx4 acc[MB][NB];
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const int m = lane & 15;
-    const int kk = lane >> 4;
-
-    for (int tap = 0; tap < TAPS; ++tap) {
-        if (tap < TAPS - 1) {
-            WV_LOAD_B(tap + 1)   // in flight while this tap computes
-        }
-        const int dy = TAPS == 1 ? 1 : tap / 3;
-        const int dx = TAPS == 1 ? 1 : tap - dy * 3;
-        const float* arow0 = lds_in + ((row0 + dy) * HALO_W + m + dx) * STRIDE + kk * 4;
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            float4 av[MB];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-                av[mb] = *reinterpret_cast<const float4*>(arow0 + mb * HALO_W * STRIDE + cb * 16);
-            float4 bv[NB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) bv[nb] = lds_w[(cb * NB + nb) * 64 + lane];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].x, bv[nb].x,
-                                                                       acc[mb][nb], 0, 0, 0);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].y, bv[nb].y,
-                                                                       acc[mb][nb], 0, 0, 0);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].z, bv[nb].z,
-                                                                       acc[mb][nb], 0, 0, 0);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb].w, bv[nb].w,
-                                                                       acc[mb][nb], 0, 0, 0);
-                }
-        }
-        if (tap < TAPS - 1) {
-            __syncthreads();   // every wave is done with this tap's B
-            WV_STORE_B()
-            __syncthreads();
-        }
-    }
     if (SYM) {
 #pragma unroll
         for (int chunk = 0; chunk < 3; ++chunk) {
@@ -212,9 +274,6 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
             }
         }
     }
-
-#undef WV_LOAD_B
-#undef WV_STORE_B
 
     // ---- epilogues.  Lane holds D[4*(lane/16) + i][lane % 16] of each block. ----
     const int col = lane & 15;
@@ -311,39 +370,44 @@ __device__ __forceinline__ void conv_tile_f32(const MfmaLayer& L, const ConvArgs
             }
         }
     }
-}
-
-template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_f32(const MfmaLayer L, const ConvArgs a) {
-    conv_tile_f32<CIN, NB, SYM, MODE, TAPS>(L, a, blockIdx.x, blockIdx.y);
-}
-
-// Persistent form: a fixed grid walks the work items of several segments (each
-// its own planes, sizes, buffers and weights), item = blockIdx.x + k gridDim.x.
-// Segment s covers items [item0, item0 + tiles * columns); its item i is tile
-// i % tiles of column i / tiles.  Static assignment: no atomics, same bits.
-template <int CIN, int NB, bool SYM, int MODE, int TAPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_f32_seg(const ConvSeg* __restrict__ segs, int nseg,
-                                                    long long total) {
-    for (long long it = blockIdx.x; it < total; it += gridDim.x) {
-        int lo = 0, hi = nseg;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (segs[mid].item0 <= it) lo = mid; else hi = mid;
-        }
-        const ConvSeg& S = segs[lo];
-        const long long local = it - S.item0;
-        const long long ntiles = (long long)S.a.tiles_x * S.a.tiles_y * S.a.N;
-        conv_tile_f32<CIN, NB, SYM, MODE, TAPS>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
-        __syncthreads();
+        si = sn;
     }
+#undef WV_SEG
+#undef WV_LOAD_B
+#undef WV_STORE_B
+#undef WV_LOAD_H
+#undef WV_LOAD_S
+}
+
+// Resident workgroups of one instantiation on the whole device (queried once).
+template <int CIN, int NB, bool SYM, int MODE, int TAPS, bool MULTI>
+int resident_f32() {
+    static int n = 0;
+    if (n == 0) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv3x3_f32p<CIN, NB, SYM, MODE, TAPS, MULTI>, 256,
+                                                         0) != hipSuccess ||
+            per_cu < 1)
+            return 256;
+        n = per_cu * cus;
+    }
+    return n;
 }
 
 template <int CIN, int NB, bool SYM, int MODE, int TAPS = 9>
 hipError_t launch_t(const MfmaLayer& L, const ConvArgs& a, hipStream_t s) {
+    ConvSeg one{};
+    one.L = L;
+    one.a = a;
+    one.item0 = 0;
     const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
-    dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
-    hipLaunchKernelGGL((conv3x3_mfma_f32<CIN, NB, SYM, MODE, TAPS>), grid, dim3(256), 0, s, L, a);
+    const long long total = (long long)a.tiles_x * a.tiles_y * a.N * ncols;
+    const long long res = resident_f32<CIN, NB, SYM, MODE, TAPS, false>();
+    const unsigned grid = (unsigned)(total < res ? total : res);
+    hipLaunchKernelGGL((conv3x3_f32p<CIN, NB, SYM, MODE, TAPS, false>), dim3(grid), dim3(256), 0, s, nullptr, 0, one,
+                       total);
     return hipGetLastError();
 }
 
@@ -393,8 +457,11 @@ hipError_t dispatch_nb(const MfmaLayer& L, int mode, int taps, const ConvArgs& a
 
 template <int CIN, int NB, bool SYM, int MODE, int TAPS = 9>
 hipError_t seg_t(const ConvSeg* segs, int nseg, long long total, int grid, hipStream_t s) {
-    hipLaunchKernelGGL((conv3x3_mfma_f32_seg<CIN, NB, SYM, MODE, TAPS>), dim3(grid), dim3(256), 0, s, segs,
-                       nseg, total);
+    const long long res = resident_f32<CIN, NB, SYM, MODE, TAPS, true>();
+    long long g = grid < res ? grid : res;
+    if (g > total) g = total;
+    hipLaunchKernelGGL((conv3x3_f32p<CIN, NB, SYM, MODE, TAPS, true>), dim3((unsigned)g), dim3(256), 0, s, segs,
+                       nseg, ConvSeg{}, total);
     return hipGetLastError();
 }
 
