@@ -32,15 +32,15 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X den
 
 
 # HBM bytes per context-conv launch from rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0), the
-# factors being what each counter reads for a plain 1 GiB device copy; averaged over the 663
-# launches of three 512x768x3 decodes.  Valid only for the conv sources with these sha256.
+# factors being what each counter reads for a plain 1 GiB device copy; averaged over the 1326
+# launches of six 512x768x3 decodes.  Valid only for the conv sources with these sha256.
 TRAFFIC_SOURCES = {
-    "paper_2405_12631_amd/csrc/wv_conv.hip": "0c75c2738701b7f58744f114f4430a55fd404187836450b942d3b72b722c31dd",
-    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "88ef0b73956dab517ad50582f70079d856d5d8fe914a1fe7a6caa12d2bb83acf",
+    "paper_2405_12631_amd/csrc/wv_conv.hip": "d3eee93ec0bed9bcdec7435597399b21ddf5b9f1d5b36090ad4432335fb7ef01",
+    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "5bf28e714fc85affbd182e21efa0b5d6eee5081b24d424b081d1a3f4b6c72d0e",
     "paper_2405_12631_amd/csrc/wv_device.h": "b20ce3ff0225e18b14ad70a1560cf9a9bcc2c4b28cfb200f15dd07098e331a8e",
-    "paper_2405_12631_amd/csrc/wv_internal.h": "ceef266fead583a11cee5c5340318c9938bc13b002a260937f5688aa65621e92",
+    "paper_2405_12631_amd/csrc/wv_internal.h": "ec3f68cc3eaef114833a80b55eda55a35887d94c372af484476205b6fb4880b5",
 }
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 53.94e6, "bf16": 28.57e6, "fp8": 17.21e6}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 57.75e6, "bf16": 28.28e6, "fp8": 17.00e6}
 
 
 def measured_traffic(precision):
@@ -496,7 +496,7 @@ def main():
     ctx_time = ctx_ms.sum(axis=1).mean() * 1e-3
     n_ctx_launch = nsub * (cfg["ctx_layers"] * 4) + nsub      # step layers + one LSTM per subband
     peak = MFMA_PEAK_TFLOPS[args.precision]
-    kname = {"fp32": "conv3x3_mfma_f32", "bf16": "conv3x3_mfma_bf16",
+    kname = {"fp32": "conv3x3_f32p", "bf16": "conv3x3_mfma_bf16",
              "fp8": "conv3x3_mfma_bf16 (e4m3 form)"}[args.precision]
     roof = dict(bound="mfma", achieved=round(ctx_flops / ctx_time / 1e12, 3),
                 peak=peak, unit="TFLOP/s",
