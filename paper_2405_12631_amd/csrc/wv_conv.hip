@@ -40,11 +40,13 @@ struct ItemPosF {
     int n, r0, c0, ycol;
 };
 
-__device__ __forceinline__ ItemPosF item_pos_f32(const ConvArgs& a, long long local) {
+template <int NB, int MODE>
+__device__ __forceinline__ ItemPosF item_pos_f32(const MfmaLayer& L, const ConvArgs& a, long long local) {
     const long long ntiles = (long long)a.tiles_x * a.tiles_y * a.N;
-    int t = (int)(local % ntiles);
+    long long tl;
     ItemPosF p;
-    p.ycol = (int)(local / ntiles);
+    conv_item_order(local, ntiles, MODE == CONV_HEAD ? 1 : L.nbt / NB, tl, p.ycol);
+    int t = (int)tl;
     const int tx = t % a.tiles_x;
     t /= a.tiles_x;
     const int ty = t % a.tiles_y;
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     int si = seg_index(it);
     {
         const ConvSeg& S0 = WV_SEG(si);
-        const ItemPosF P0 = item_pos_f32(S0.a, it - S0.item0);
+        const ItemPosF P0 = item_pos_f32<NB, MODE>(S0.L, S0.a, it - S0.item0);
 #pragma unroll
         for (int k = 0; k < NH; ++k) WV_LOAD_H(S0.a, P0, k)
         WV_LOAD_S(S0.a, S0.L, P0)
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         const ConvSeg& S = WV_SEG(si);
         const MfmaLayer& L = S.L;
         const ConvArgs& a = S.a;
-        const ItemPosF P = item_pos_f32(a, it - S.item0);
+        const ItemPosF P = item_pos_f32<NB, MODE>(L, a, it - S.item0);
         const int n = P.n, r0 = P.r0, c0 = P.c0, ycol = P.ycol;
         const int nblk0 = ycol * NB;
         const int row0 = wave * 2 + (MODE == CONV_HEAD ? (a.step >> 1) : 0);   // first tile row of this wave
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         const bool has_next = nx < total;
         const int sn = has_next ? seg_index(nx) : si;
         const ConvSeg& SN = WV_SEG(sn);
-        const ItemPosF PN = item_pos_f32(SN.a, nx - SN.item0);
+        const ItemPosF PN = item_pos_f32<NB, MODE>(SN.L, SN.a, nx - SN.item0);
 
         floatx4 acc[MB][NB];
 #pragma unroll
@@ -405,7 +407,9 @@ hipError_t launch_t(const MfmaLayer& L, const ConvArgs& a, hipStream_t s) {
     const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
     const long long total = (long long)a.tiles_x * a.tiles_y * a.N * ncols;
     const long long res = resident_f32<CIN, NB, SYM, MODE, TAPS, false>();
-    const unsigned grid = (unsigned)(total < res ? total : res);
+    long long g = total < res ? total : res;
+    if (g < total && g >= 8) g &= ~7ll;   // columns of a tile on one XCD (conv_item_order)
+    const unsigned grid = (unsigned)g;
     hipLaunchKernelGGL((conv3x3_f32p<CIN, NB, SYM, MODE, TAPS, false>), dim3(grid), dim3(256), 0, s, nullptr, 0, one,
                        total);
     return hipGetLastError();
@@ -460,6 +464,7 @@ hipError_t seg_t(const ConvSeg* segs, int nseg, long long total, int grid, hipSt
     const long long res = resident_f32<CIN, NB, SYM, MODE, TAPS, true>();
     long long g = grid < res ? grid : res;
     if (g > total) g = total;
+    if (g < total && g >= 8) g &= ~7ll;   // columns of a tile on one XCD (conv_item_order)
     hipLaunchKernelGGL((conv3x3_f32p<CIN, NB, SYM, MODE, TAPS, true>), dim3((unsigned)g), dim3(256), 0, s, segs,
                        nseg, ConvSeg{}, total);
     return hipGetLastError();

@@ -355,7 +355,11 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 template <int CIN, int NB, bool SYM, int MODE, bool F8>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void conv3x3_mfma_bf16(
     const MfmaLayer16 L, const ConvArgs a) {
-    conv_tile_bf16<CIN, NB, SYM, MODE, F8>(L, a, blockIdx.x, blockIdx.y);
+    long long tile;
+    int ycol;
+    conv_item_order(blockIdx.x, (long long)a.tiles_x * a.tiles_y * a.N, MODE == CONV_HEAD ? 1 : L.nbt / NB, tile,
+                    ycol);
+    conv_tile_bf16<CIN, NB, SYM, MODE, F8>(L, a, (int)tile, ycol);
 }
 
 // Persistent multi-segment form (see the FP32 kernel).
@@ -370,8 +374,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         }
         const ConvSeg16& S = segs[lo];
         const long long local = it - S.item0;
-        const long long ntiles = (long long)S.a.tiles_x * S.a.tiles_y * S.a.N;
-        conv_tile_bf16<CIN, NB, SYM, MODE, F8>(S.L, S.a, (int)(local % ntiles), (int)(local / ntiles));
+        long long tile;
+        int ycol;
+        conv_item_order(local, (long long)S.a.tiles_x * S.a.tiles_y * S.a.N, MODE == CONV_HEAD ? 1 : S.L.nbt / NB,
+                        tile, ycol);
+        conv_tile_bf16<CIN, NB, SYM, MODE, F8>(S.L, S.a, (int)tile, ycol);
         __syncthreads();
     }
 }
@@ -382,7 +389,7 @@ hipError_t launch_t(const MfmaLayer16& L, const ConvArgs& a0, hipStream_t s) {
     a.tiles_x = (a.w + TW - 1) / TW;
     a.tiles_y = (a.h + TH - 1) / TH;
     const int ncols = (MODE == CONV_HEAD) ? 1 : L.nbt / NB;
-    dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N), (unsigned)ncols);
+    dim3 grid((unsigned)(a.tiles_x * a.tiles_y * a.N * ncols));
     hipLaunchKernelGGL((conv3x3_mfma_bf16<CIN, NB, SYM, MODE, F8>), grid, dim3(256), 0, s, L, a);
     return hipGetLastError();
 }
@@ -419,6 +426,7 @@ hipError_t dispatch_nb(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStr
 
 template <int CIN, int NB, bool SYM, int MODE, bool F8>
 hipError_t seg_t(const ConvSeg16* segs, int nseg, long long total, int grid, hipStream_t s) {
+    if (grid < total && grid >= 8) grid &= ~7;   // columns of a tile on one XCD (conv_item_order)
     hipLaunchKernelGGL((conv3x3_mfma_bf16_seg<CIN, NB, SYM, MODE, F8>), dim3(grid), dim3(256), 0, s, segs, nseg,
                        total);
     return hipGetLastError();

@@ -101,6 +101,29 @@ struct ConvArgs {
     float sigma_min;
 };
 
+// Order of the work items (tile, channel column) of a conv launch with ncols
+// columns per tile.  Workgroup i runs on XCD i mod 8, and every XCD has its own
+// L2.  Here the ncols items of one tile get indices 8 apart and consecutive in
+// their XCD's dispatch order.  In a grid of a multiple of 8 workgroups (or one
+// item per workgroup) the columns of a tile then run at the same time on one
+// XCD, and the tile's input halo comes from HBM once instead of ncols times.
+// Tiles past the last full group of 8 keep the plain order.  The mapping is a
+// bijection of [0, ntiles * ncols), so the results do not depend on it.
+__device__ __forceinline__ void conv_item_order(long long local, long long ntiles, int ncols, long long& tile,
+                                                int& ycol) {
+    const long long t8 = ntiles & ~7ll;
+    if (local < t8 * ncols) {
+        const long long q = local >> 3;
+        ycol = (int)(q % ncols);
+        tile = (q / ncols) * 8 + (local & 7);
+    } else {
+        const long long r = local - t8 * ncols;
+        const long long rest = ntiles - t8;
+        ycol = (int)(r / rest);
+        tile = t8 + r % rest;
+    }
+}
+
 // One segment of a persistent multi-segment conv launch: its own layer (weights),
 // arguments and first work item (items = tiles * columns of 16 NB channels).
 struct ConvSeg {

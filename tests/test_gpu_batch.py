@@ -132,3 +132,37 @@ def test_single_image_graph_replays_equal_eager(prec):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(q, ref_q) and torch.equal(xhat, ref_x)
+
+
+def test_wide_and_narrow_channel_blocking_bitwise():
+    """The number of 16-channel output blocks per workgroup (and with it the item
+    order over tiles and columns) never changes a result: a plan with four blocks
+    per item everywhere (many segments, ragged subbands) and single-image calls on
+    a 512x768 image (whose level-1 subbands take four blocks by the default rule)
+    give the bits of a plan with two blocks everywhere (BF16 model)."""
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16
+    say("wide vs narrow channel blocking")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    sizes = [(512, 768), (64, 96), (48, 80), (64, 96)]
+    imgs = _images(sizes, seed=41)
+    narrow = B.Batch(model, sizes, nb_table=[2, 2, 2, 2])
+    wide = B.Batch(model, sizes, nb_table=[4, 4, 4, 4])
+    narrow.load_images(imgs)
+    wide.load_images(imgs)
+    for b in range(len(narrow.q)):
+        assert torch.equal(narrow.q[b], wide.q[b])
+    gb = narrow.where[0][0]
+    ws = codec.Workspace(model, 3, 512, 768)
+    q = narrow.q[gb].clone()
+    K = cfg["mix_k"]
+    for i in range(narrow.nsub):
+        for g in range(4):
+            a = narrow.context_params(i, g).clone()
+            b = wide.context_params(i, g).clone()
+            assert torch.equal(a, b), (i, g)
+            n, first = narrow.rows(i, g)
+            ref = codec.context_params(model, q, ws, i, g).reshape(-1)
+            lo = first[gb] * 3 * K
+            assert torch.equal(a[lo:lo + ref.numel()], ref), (i, g)
