@@ -8,7 +8,8 @@ host entropy coder would return are taken from a device buffer), then
 dequantisation and synthesis.  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--precision fp32|bf16] [--workload ycbcr512x768|batch64_mixed|serve_mix]
+                    [--precision fp32|bf16|fp8]
+                    [--workload ycbcr512x768|batch64_mixed|serve_mix|precision_report|coder512x768|hbm_copy]
 
 The default is the FP32 batch-1 512x768 workload.  --workload batch64_mixed
 times a mixed-size batch of 64 images (BF16 context, persistent launches,
@@ -35,12 +36,12 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X den
 # factors being what each counter reads for a plain 1 GiB device copy; averaged over the 1326
 # launches of six 512x768x3 decodes.  Valid only for the conv sources with these sha256.
 TRAFFIC_SOURCES = {
-    "paper_2405_12631_amd/csrc/wv_conv.hip": "d3eee93ec0bed9bcdec7435597399b21ddf5b9f1d5b36090ad4432335fb7ef01",
-    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "5bf28e714fc85affbd182e21efa0b5d6eee5081b24d424b081d1a3f4b6c72d0e",
+    "paper_2405_12631_amd/csrc/wv_conv.hip": "5d304fb56ef2d1a598c543b7131b29868c1c1e90e3e20e895c9a3768591f50d9",
+    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "11051aeed6d21b2fbd4ed28d9f630866de3ee43f8eedcbba202e95c90cdb4061",
     "paper_2405_12631_amd/csrc/wv_device.h": "b20ce3ff0225e18b14ad70a1560cf9a9bcc2c4b28cfb200f15dd07098e331a8e",
-    "paper_2405_12631_amd/csrc/wv_internal.h": "ec3f68cc3eaef114833a80b55eda55a35887d94c372af484476205b6fb4880b5",
+    "paper_2405_12631_amd/csrc/wv_internal.h": "28fe2efef9fdeefc93f7dc93002e459af2d845b0a14881e31cc954149aba3f79",
 }
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 57.75e6, "bf16": 28.28e6, "fp8": 17.00e6}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 49.22e6, "bf16": 25.64e6, "fp8": 14.94e6}
 
 
 def measured_traffic(precision):
@@ -369,6 +370,20 @@ def bench_coder(args):
     print(json.dumps(out))
 
 
+def hbm_copy():
+    """Three plain device copies of 1 GiB: the reference a profiler's FETCH_SIZE and
+    WRITE_SIZE readings are scaled by (run under rocprofv3 --pmc, one counter a run)."""
+    import torch
+    n = 1 << 28   # floats: 1 GiB
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "hbm_copy", "copies": 3, "bytes_each": 4 * n}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,7 +394,7 @@ def main():
                     help="context-conv precision (lifting and CDFs stay FP32); default fp32, "
                          "bf16 for the batched and serving workloads")
     ap.add_argument("--workload", choices=["ycbcr512x768", "batch64_mixed", "serve_mix",
-                                           "precision_report", "coder512x768"],
+                                           "precision_report", "coder512x768", "hbm_copy"],
                     default="ycbcr512x768")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="arrival window of the serving run")
     ap.add_argument("--serve-drain", type=float, default=20.0, help="time allowed to drain after it")
@@ -390,6 +405,8 @@ def main():
         print("bench.py measures one GPU; this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "hbm_copy":
+        return hbm_copy()
     if args.workload == "batch64_mixed":
         args.precision = args.precision or "bf16"
         return bench_batch(args)
