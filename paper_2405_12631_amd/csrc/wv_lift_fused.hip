@@ -8,6 +8,10 @@
 // overwrites the first layer's buffer), the last layer and the update on the
 // 8 x 16 outputs.  Positions outside the array are zero in every layer, which
 // is exactly the per-layer zero padding of the definition.
+//
+// Persistent: a workgroup loads the three layers' weights into LDS once and
+// then walks tiles blockIdx.x, + gridDim.x, ...; the next tile's z halo is
+// read into registers while this tile's layer-2 MFMAs run.
 #include "wv_device.h"
 #include "wv_internal.h"
 
@@ -25,7 +29,7 @@ template <int C>
 __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const MfmaLayer L2, const VecLayer L3,
                                                    const CView z, const CView A, const View out, int N,
                                                    int h, int w, int tiles_x, int tiles_y, int predict,
-                                                   float sign, int lift_int) {
+                                                   float sign, int lift_int, int total) {
     constexpr int S1 = C + 4;               // floats per position in the layer buffers
     constexpr int NP2 = BH * BW;            // 180 second-layer positions
     constexpr int MB2 = (NP2 + 15) / 16;    // 12 M blocks
@@ -41,15 +45,37 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    int t = blockIdx.x;
-    const int tx = t % tiles_x;
-    t /= tiles_x;
-    const int ty = t % tiles_y;
-    const int n = t / tiles_y;
-    const int r0 = ty * OH, c0 = tx * OW;
+    struct Tile { int n, r0, c0; };
+    auto tile_of = [&](int t) {
+        Tile T;
+        const int tx = t % tiles_x;
+        t /= tiles_x;
+        const int ty = t % tiles_y;
+        T.n = t / tiles_y;
+        T.r0 = ty * OH;
+        T.c0 = tx * OW;
+        return T;
+    };
+    // z halo of a tile, two positions per thread (ZH * ZW <= 512)
+    constexpr int NZ = (ZH * ZW + 255) / 256;
+    static_assert(NZ == 2, "z halo split");
+    float zv_next[NZ];
+    auto load_z = [&](const Tile& T) {
+        const float* zp = z.p + (long long)T.n * z.ps;
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+            const int i = tid + k * 256;
+            const int r = T.r0 - 3 + i / ZW, c = T.c0 - 3 + i % ZW;
+            zv_next[k] = 0.f;
+            if (i < ZH * ZW && r >= 0 && r < h && c >= 0 && c < w)
+                zv_next[k] = zp[(long long)r * z.rs + (long long)c * z.cs];
+        }
+    };
 
     static_assert(MBW * 4 == MB2, "the four waves split the M blocks evenly");
-    // weights and the z halo; every thread's loads are in flight before its first store
+    if ((int)blockIdx.x >= total) return;
+    load_z(tile_of(blockIdx.x));
+    // weights, once per workgroup; every thread's loads are in flight before its first store
     {
         constexpr int NW = (9 * CB * NBT * 64 + 255) / 256;
         float4 wv[NW];
@@ -73,11 +99,14 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
         b1s[i] = L1.bias[i];
         b2s[i] = L2.bias[i];
     }
-    const float* zp = z.p + (long long)n * z.ps;
-    for (int i = tid; i < ZH * ZW; i += 256) {
-        const int r = r0 - 3 + i / ZW, c = c0 - 3 + i % ZW;
-        zs[i] = (r >= 0 && r < h && c >= 0 && c < w) ? zp[(long long)r * z.rs + (long long)c * z.cs] : 0.f;
-    }
+
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const Tile T = tile_of(t);
+    const int n = T.n, r0 = T.r0, c0 = T.c0;
+    __syncthreads();   // the previous tile is done with zs and act (and the weights are in LDS)
+#pragma unroll
+    for (int k = 0; k < NZ; ++k)
+        if (tid + k * 256 < ZH * ZW) zs[tid + k * 256] = zv_next[k];
     __syncthreads();
 
     // layer 1 on the 12 x 20 region: tanh(b1 + sum_tap w1 z), zero outside the array
@@ -139,6 +168,7 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
             acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].w, bfr[cur][nb].w, acc[j][nb], 0, 0, 0); \
         }                                                                                           \
     }
+    if (t + (int)gridDim.x < total) load_z(tile_of(t + gridDim.x));   // in flight during the MFMAs
     WV_LOAD_F(0, 0, 0)
     for (int st = 0; st + 1 < 9 * CB; st += 2) {   // pairs of steps: buffer 0, then buffer 1
         WV_STEP(0, st)
@@ -199,6 +229,22 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
             out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = av + sign * f;
         }
     }
+  }
+}
+
+template <int C>
+long long lift_resident() {
+    static long long n = 0;
+    if (n == 0) {
+        int per_cu = 0, cus = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lift_fused_k<C>, 256, 0) != hipSuccess ||
+            per_cu < 1)
+            return 256;
+        n = (long long)per_cu * cus;
+    }
+    return n;
 }
 
 }  // namespace
@@ -208,15 +254,19 @@ hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecL
                              hipStream_t s) {
     if ((long long)N * h * w == 0) return hipSuccess;
     const int tx = (w + OW - 1) / OW, ty = (h + OH - 1) / OH;
-    const dim3 grid((unsigned)(tx * ty * N));
-    if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2)
-        hipLaunchKernelGGL(lift_fused_k<32>, grid, dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx, ty,
-                           predict, sign, lift_int);
-    else if (L1.ch == 16 && L2.cin == 16 && L2.nbt == 1)
-        hipLaunchKernelGGL(lift_fused_k<16>, grid, dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx, ty,
-                           predict, sign, lift_int);
-    else
+    const long long total = (long long)tx * ty * N;
+    if (total >= (1ll << 31)) return hipErrorInvalidValue;
+    if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2) {
+        const long long g = total < lift_resident<32>() ? total : lift_resident<32>();
+        hipLaunchKernelGGL(lift_fused_k<32>, dim3((unsigned)g), dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx,
+                           ty, predict, sign, lift_int, (int)total);
+    } else if (L1.ch == 16 && L2.cin == 16 && L2.nbt == 1) {
+        const long long g = total < lift_resident<16>() ? total : lift_resident<16>();
+        hipLaunchKernelGGL(lift_fused_k<16>, dim3((unsigned)g), dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx,
+                           ty, predict, sign, lift_int, (int)total);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
