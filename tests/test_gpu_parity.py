@@ -5,8 +5,8 @@ import torch
 
 import oracle as O
 from wvgen import get_config, gradient_noise_image, sinusoid_1f_planes
-from gpu_common import (PARAM_RTOL, XHAT_ATOL, check_cdf_rows, model_for, need_gpu, param_err,
-                        q_to_device, say)
+from gpu_common import (PARAM_RTOL, REDUCED_BARS, XHAT_ATOL, check_cdf_rows, model_for, need_gpu, param_err,
+                        q_to_device, reduced_errs, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -382,21 +382,30 @@ def test_autoregressive_ll_model(name, H, W, N):
         codec.ar_decode(model, q, codec.Workspace(model, N, H, W), [bytes(ll)] + [s[0][0] for s in bad[1:]])
 
 
-def test_full_size_plane_parity_in_bench_configuration():
-    """512 x 768, the benchmark's model and launch configuration (three planes per call):
-    every parameter of plane 0 (all 13 subbands x 4 steps) and its reconstruction against
-    the oracle; the oracle runs on the GPU encoder's own symbols."""
+@pytest.fixture(scope="module")
+def full512():
+    """512 x 768 x 3 through the FP32 encoder, and the oracle's parameters of plane 0 (all 13
+    subbands x 4 steps) on the GPU encoder's own symbols."""
     need_gpu()
     from paper_2405_12631_amd import codec
-    say("full size 512x768")
     cfg = get_config("ycbcr512x768")
     model, w = model_for(cfg)
     x = sinusoid_1f_planes(512, 768, planes=3, seed=cfg["seed_image"])
     ws = codec.Workspace(model, 3, 512, 768)
     q, _, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws)
-    got = codec.params_all(model, q, ws)
     qs = O.unpack(q.cpu().numpy().astype(np.int64)[:1], cfg, 512, 768)
     ref = O.context_params_all(qs, cfg, w)
+    return dict(cfg=cfg, model=model, w=w, ws=ws, q=q, qs=qs, ref=ref, codec=codec)
+
+
+def test_full_size_plane_parity_in_bench_configuration(full512):
+    """512 x 768, the benchmark's model and launch configuration (three planes per call):
+    every parameter of plane 0 (all 13 subbands x 4 steps) and its reconstruction against
+    the oracle; the oracle runs on the GPU encoder's own symbols."""
+    say("full size 512x768")
+    F = full512
+    cfg, model, w, ws, q, qs, ref, codec = (F[k] for k in ("cfg", "model", "w", "ws", "q", "qs", "ref", "codec"))
+    got = codec.params_all(model, q, ws)
     worst = max(param_err(got[i][g][:1].cpu().numpy(), ref[i][g], 3) for i in range(13) for g in range(4))
     say("full-size worst param rel err", worst)
     assert worst <= PARAM_RTOL
@@ -405,3 +414,30 @@ def test_full_size_plane_parity_in_bench_configuration():
     xh, _ = codec.synthesize(model, ws, q=q)
     ref_x = O.synthesize(O.dequantize(qs, cfg), cfg, w)
     assert np.max(np.abs(xh[:1].cpu().numpy() - ref_x)) <= XHAT_ATOL
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_full_size_reduced_precision_against_oracle(full512, prec):
+    """The BF16 and FP8 context models at 512 x 768 x 3, where the level-1 subbands take the
+    widest channel blocking and the ConvLSTM's column blocks run in XCD order: plane 0's
+    parameters against the same oracle, within the reduced-precision bounds, and the CDF
+    rows of the last subband valid."""
+    from paper_2405_12631_amd import WV_BF16, WV_FP8
+    from wvgen import make_weights, pack_weights
+    F = full512
+    cfg, q, ref, codec = F["cfg"], F["q"], F["ref"], F["codec"]
+    say("full size 512x768", prec)
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision={"bf16": WV_BF16, "fp8": WV_FP8}[prec])
+    ws = codec.Workspace(model, 3, 512, 768)
+    got = codec.params_all(model, q, ws)
+    rels, wmax = [], 0.0
+    for i in range(13):
+        for g in range(4):
+            r, wm = reduced_errs(got[i][g][:1].cpu().numpy(), ref[i][g], cfg["mix_k"])
+            rels.append(r.ravel())
+            wmax = max(wmax, wm)
+    rel = np.concatenate(rels)
+    say(f"{prec} 512x768: mean rel {rel.mean():.3e} max {rel.max():.3e} max |dw| {wmax:.3e}")
+    assert rel.mean() < REDUCED_BARS[prec][0] and wmax < REDUCED_BARS[prec][1]
+    cdf = codec.cdf_tables(model, got[12][3][:1].contiguous())
+    check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[12][3][:1].cpu().numpy(), cfg)

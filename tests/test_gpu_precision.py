@@ -6,23 +6,12 @@ import torch
 
 import oracle as O
 from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes, gradient_noise_image
-from gpu_common import need_gpu, q_to_device, say, check_cdf_rows, TAU
+from gpu_common import REDUCED_BARS, check_cdf_rows, need_gpu, q_to_device, reduced_errs, say
 
 pytestmark = pytest.mark.gpu
 
-# No parity bar is set for reduced precision; these bounds only catch a broken
-# kernel (an FP32-accumulated BF16 conv stack stays far inside them; e4m3 has
-# 3 mantissa bits, so its per-value rounding alone reaches 6 %).
-BARS = {"bf16": (2e-2, 0.1), "fp8": (0.25, 0.5)}
-
-
-def _errs(gpu, ref, K):
-    g = np.asarray(gpu, np.float64).reshape(-1, 3 * K)
-    r = np.asarray(ref, np.float64).reshape(-1, 3 * K)
-    den = np.abs(r)
-    den[:, :2 * K] = np.maximum(den[:, :2 * K], TAU)
-    rel = np.abs(g - r) / den
-    return rel, np.abs(g[:, :K] - r[:, :K]).max(initial=0)
+BARS = REDUCED_BARS
+_errs = reduced_errs
 
 
 def _prec(name):
