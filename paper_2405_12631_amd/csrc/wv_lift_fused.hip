@@ -1,13 +1,18 @@
 // One predict/update filter application in a single kernel (Sec. 3.1):
 //   out = A + sign * f,  f = z + N(z) (predict) or z/2 + N(z) (update),
 //   N = conv3x3(C -> 1) . tanh . conv3x3(C -> C) . tanh . conv3x3(1 -> C),
-// every conv zero-padded at the array border.  A workgroup owns an 8 x 16
-// output tile and keeps the whole chain in LDS: z on a 14 x 22 halo, the
-// first layer on 12 x 20 positions (vector ALUs), the second on 10 x 18
-// positions as an implicit GEMM on v_mfma_f32_16x16x4f32 (its output then
-// overwrites the first layer's buffer), the last layer and the update on the
-// 8 x 16 outputs.  Positions outside the array are zero in every layer, which
-// is exactly the per-layer zero padding of the definition.
+// every conv zero-padded at the array border.  A workgroup owns an OH x OW
+// output tile and keeps the whole chain in LDS: z on an (OH+6) x (OW+6) halo,
+// the first layer on (OH+4) x (OW+4) positions (vector ALUs), the second on
+// (OH+2) x (OW+2) positions as an implicit GEMM on v_mfma_f32_16x16x4f32 (its
+// output then overwrites the first layer's buffer), the last layer and the
+// update on the outputs.  Positions outside the array are zero in every layer,
+// which is exactly the per-layer zero padding of the definition.
+//
+// Tile: 8 x 16 outputs and 4 waves (two workgroups per CU), or, for the
+// 32-channel filters over large arrays, 16 x 32 outputs and 8 waves (layer 2
+// on 612 positions = 39 of the 40 M blocks the waves take, 1.25x the outputs,
+// where the 8 x 16 tile pays 1.5x).
 //
 // Persistent: a workgroup loads the three layers' weights into LDS once and
 // then walks tiles blockIdx.x, + gridDim.x, ...; the next tile's z halo is
@@ -20,22 +25,22 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int OH = 8, OW = 16;
-constexpr int ZH = OH + 6, ZW = OW + 6;   // z halo
-constexpr int AH = OH + 4, AW = OW + 4;   // first layer region
-constexpr int BH = OH + 2, BW = OW + 2;   // second layer region
-
-template <int C>
-__global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const MfmaLayer L2, const VecLayer L3,
-                                                   const CView z, const CView A, const View out, int N,
-                                                   int h, int w, int tiles_x, int tiles_y, int predict,
-                                                   float sign, int lift_int, int total) {
+template <int C, int OH, int OW, int NWV>
+__global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, const MfmaLayer L2, const VecLayer L3,
+                                                        const CView z, const CView A, const View out, int N,
+                                                        int h, int w, int tiles_x, int tiles_y, int predict,
+                                                        float sign, int lift_int, int total) {
+    constexpr int NT = 64 * NWV;            // threads
+    constexpr int ZH = OH + 6, ZW = OW + 6;   // z halo
+    constexpr int AH = OH + 4, AW = OW + 4;   // first layer region
+    constexpr int BH = OH + 2, BW = OW + 2;   // second layer region
     constexpr int S1 = C + 4;               // floats per position in the layer buffers
-    constexpr int NP2 = BH * BW;            // 180 second-layer positions
-    constexpr int MB2 = (NP2 + 15) / 16;    // 12 M blocks
+    constexpr int NP2 = BH * BW;            // second-layer positions
+    constexpr int MB2 = (NP2 + 15) / 16;    // M blocks
     constexpr int CB = C / 16;              // K chunks (16 channels) per tap
     constexpr int NBT = C / 16;             // output blocks of 16
-    constexpr int MBW = (MB2 + 3) / 4;      // M blocks per wave (3)
+    constexpr int MBW = (MB2 + NWV - 1) / NWV;   // M blocks per wave (the last ones may be padding)
+    static_assert((2 * OH * OW) % NT == 0, "layer 3 takes two threads per output in whole rounds");
     __shared__ float zs[ZH * ZW];
     __shared__ __attribute__((aligned(16))) float act[AH * AW * S1];   // layer 1, then layer 2
     __shared__ __attribute__((aligned(16))) float4 w2s[9 * CB * NBT * 64];
@@ -56,15 +61,14 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
         T.c0 = tx * OW;
         return T;
     };
-    // z halo of a tile, two positions per thread (ZH * ZW <= 512)
-    constexpr int NZ = (ZH * ZW + 255) / 256;
-    static_assert(NZ == 2, "z halo split");
+    // z halo of a tile, NZ positions per thread
+    constexpr int NZ = (ZH * ZW + NT - 1) / NT;
     float zv_next[NZ];
     auto load_z = [&](const Tile& T) {
         const float* zp = z.p + (long long)T.n * z.ps;
 #pragma unroll
         for (int k = 0; k < NZ; ++k) {
-            const int i = tid + k * 256;
+            const int i = tid + k * NT;
             const int r = T.r0 - 3 + i / ZW, c = T.c0 - 3 + i % ZW;
             zv_next[k] = 0.f;
             if (i < ZH * ZW && r >= 0 && r < h && c >= 0 && c < w)
@@ -72,30 +76,29 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
         }
     };
 
-    static_assert(MBW * 4 == MB2, "the four waves split the M blocks evenly");
     if ((int)blockIdx.x >= total) return;
     load_z(tile_of(blockIdx.x));
     // weights, once per workgroup; every thread's loads are in flight before its first store
     {
-        constexpr int NW = (9 * CB * NBT * 64 + 255) / 256;
+        constexpr int NW = (9 * CB * NBT * 64 + NT - 1) / NT;
         float4 wv[NW];
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-            const int i = tid + k * 256;
+            const int i = tid + k * NT;
             wv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
             if (i < 9 * CB * NBT * 64) wv[k] = reinterpret_cast<const float4*>(L2.w)[i];
         }
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-            const int i = tid + k * 256;
+            const int i = tid + k * NT;
             if (i < 9 * CB * NBT * 64) w2s[i] = wv[k];
         }
     }
-    for (int i = tid; i < 9 * C; i += 256) {
+    for (int i = tid; i < 9 * C; i += NT) {
         w1s[i] = L1.w[i];
         w3s[i] = L3.w[i];
     }
-    for (int i = tid; i < C; i += 256) {
+    for (int i = tid; i < C; i += NT) {
         b1s[i] = L1.bias[i];
         b2s[i] = L2.bias[i];
     }
@@ -106,11 +109,11 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     __syncthreads();   // the previous tile is done with zs and act (and the weights are in LDS)
 #pragma unroll
     for (int k = 0; k < NZ; ++k)
-        if (tid + k * 256 < ZH * ZW) zs[tid + k * 256] = zv_next[k];
+        if (tid + k * NT < ZH * ZW) zs[tid + k * NT] = zv_next[k];
     __syncthreads();
 
-    // layer 1 on the 12 x 20 region: tanh(b1 + sum_tap w1 z), zero outside the array
-    for (int i = tid; i < AH * AW * (C / 4); i += 256) {
+    // layer 1 on the (OH+4) x (OW+4) region: tanh(b1 + sum_tap w1 z), zero outside the array
+    for (int i = tid; i < AH * AW * (C / 4); i += NT) {
         const int pos = i / (C / 4);
         const int c4 = (i - pos * (C / 4)) * 4;
         const int ay = pos / AW, ax = pos % AW;
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     }
     __syncthreads();
 
-    // layer 2 on the 10 x 18 region: MFMA over K = 9 taps x C channels
+    // layer 2 on the (OH+2) x (OW+2) region: MFMA over K = 9 taps x C channels
     const int m = lane & 15;
     const int kk = lane >> 4;
     floatx4 acc[MBW][NBT];
@@ -199,9 +202,11 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
     __syncthreads();
 
     // layer 3 and the lifting update: two threads per output, halves of the channels
-    {
-        const int o = tid >> 1;
-        const int half = tid & 1;
+#pragma unroll
+    for (int task0 = 0; task0 < 2 * OH * OW; task0 += NT) {
+        const int task = task0 + tid;
+        const int o = task >> 1;
+        const int half = task & 1;
         const int oy = o / OW, ox = o % OW;
         float s = 0.f;
 #pragma unroll
@@ -232,19 +237,33 @@ __global__ __launch_bounds__(256) void lift_fused_k(const VecLayer L1, const Mfm
   }
 }
 
-template <int C>
+template <int C, int OH, int OW, int NWV>
 long long lift_resident() {
     static long long n = 0;
     if (n == 0) {
         int per_cu = 0, cus = 0, dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lift_fused_k<C>, 256, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lift_fused_k<C, OH, OW, NWV>, 64 * NWV, 0) !=
+                hipSuccess ||
             per_cu < 1)
             return 256;
         n = (long long)per_cu * cus;
     }
     return n;
+}
+
+template <int C, int OH, int OW, int NWV>
+hipError_t lift_launch(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A, View out, int N,
+                       int h, int w, int predict, float sign, int lift_int, hipStream_t s) {
+    const int tx = (w + OW - 1) / OW, ty = (h + OH - 1) / OH;
+    const long long total = (long long)tx * ty * N;
+    if (total >= (1ll << 31)) return hipErrorInvalidValue;
+    const long long res = lift_resident<C, OH, OW, NWV>();
+    const long long g = total < res ? total : res;
+    hipLaunchKernelGGL((lift_fused_k<C, OH, OW, NWV>), dim3((unsigned)g), dim3(64 * NWV), 0, s, L1, L2, L3, z, A, out,
+                       N, h, w, tx, ty, predict, sign, lift_int, (int)total);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -253,21 +272,19 @@ hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecL
                              View out, int N, int h, int w, int predict, float sign, int lift_int,
                              hipStream_t s) {
     if ((long long)N * h * w == 0) return hipSuccess;
-    const int tx = (w + OW - 1) / OW, ty = (h + OH - 1) / OH;
-    const long long total = (long long)tx * ty * N;
-    if (total >= (1ll << 31)) return hipErrorInvalidValue;
     if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2) {
-        const long long g = total < lift_resident<32>() ? total : lift_resident<32>();
-        hipLaunchKernelGGL(lift_fused_k<32>, dim3((unsigned)g), dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx,
-                           ty, predict, sign, lift_int, (int)total);
-    } else if (L1.ch == 16 && L2.cin == 16 && L2.nbt == 1) {
-        const long long g = total < lift_resident<16>() ? total : lift_resident<16>();
-        hipLaunchKernelGGL(lift_fused_k<16>, dim3((unsigned)g), dim3(256), 0, s, L1, L2, L3, z, A, out, N, h, w, tx,
-                           ty, predict, sign, lift_int, (int)total);
-    } else {
-        return hipErrorInvalidValue;
+        // The 16 x 32 tile needs one 8-wave workgroup per CU, whose phases (vector layer 1, MFMA
+        // layer 2, layer 3) no longer overlap with a second workgroup's; it pays off only where
+        // its lower recompute has many rounds of tiles to work on (measured: 1088 x 1920 planes
+        // 5.37 -> 4.63 ms per synthesis, 512 x 768 planes 1.26 -> 1.52 ms).
+        const long long big = (long long)((w + 31) / 32) * ((h + 15) / 16) * N;
+        if (big >= 2048)
+            return lift_launch<32, 16, 32, 8>(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s);
+        return lift_launch<32, 8, 16, 4>(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s);
     }
-    return hipGetLastError();
+    if (L1.ch == 16 && L2.cin == 16 && L2.nbt == 1)
+        return lift_launch<16, 8, 16, 4>(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace wv

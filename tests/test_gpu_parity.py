@@ -441,3 +441,24 @@ def test_full_size_reduced_precision_against_oracle(full512, prec):
     assert rel.mean() < REDUCED_BARS[prec][0] and wmax < REDUCED_BARS[prec][1]
     cdf = codec.cdf_tables(model, got[12][3][:1].contiguous())
     check_cdf_rows(cdf.cpu().numpy().view(np.uint16), got[12][3][:1].cpu().numpy(), cfg)
+
+
+def test_lifting_tile_forms_bitwise():
+    """Analysis and synthesis of six 512 x 768 planes in one call take the 16 x 32-output lifting
+    tile (at least 2048 such tiles per filter launch); three planes take the 8 x 16 one, whose
+    results the full-size oracle test covers.  Both tile forms keep each output's arithmetic, so
+    the symbols and the reconstruction of the shared planes are bitwise equal."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("lifting tile forms")
+    cfg = get_config("ycbcr512x768")
+    model, _ = model_for(cfg)
+    x = np.concatenate([sinusoid_1f_planes(512, 768, planes=3, seed=s) for s in (7, 8)])
+    ws6 = codec.Workspace(model, 6, 512, 768)
+    ws3 = codec.Workspace(model, 3, 512, 768)
+    q6, y6, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws6, want_y=True)
+    q3, y3, _ = codec.analyze(model, torch.from_numpy(x[:3]).cuda(), ws3, want_y=True)
+    assert torch.equal(q6[:3], q3) and torch.equal(y6[:3], y3)
+    x6, _ = codec.synthesize(model, ws6, q=q6)
+    x3, _ = codec.synthesize(model, ws3, q=q3)
+    assert torch.equal(x6[:3], x3)
