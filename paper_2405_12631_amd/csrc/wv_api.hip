@@ -305,7 +305,13 @@ MfmaRef pack_mfma8(PackBuf& pb, const float* blob, const ConvShape& s, int has_s
     const int cin_total = s.cin;
     const float* W = blob + s.w_off;
     const float* B = blob + s.b_off;
-    r.w = pb.add((size_t)9 * CC * r.nbt * 64 * 2);          // 8 bytes = 2 floats per lane
+    // Step-stack layers with 64 input channels and no symbol channel (the kernel's K128 rule):
+    // [5 steps][nbt][64 lanes][32 bytes], step s = taps 2s, 2s + 1 (tap 9 zero), lane group
+    // kk = tap 2s + kk/2, channels 32 (kk % 2) + j (the K = 128 MFMA); otherwise
+    // [9 taps][cin/32][nbt][64 lanes][8 bytes] (the K = 32 MFMA).
+    const bool k128 = r.cin == 64 && !has_sym && !lstm;
+    r.w = k128 ? pb.add((size_t)5 * r.nbt * 64 * 8)          // 32 bytes = 8 floats per lane
+               : pb.add((size_t)9 * CC * r.nbt * 64 * 2);   // 8 bytes = 2 floats per lane
     r.wsym = has_sym ? pb.add((size_t)r.nbt * 64 * 4) : 0;
     r.bias = pb.add((size_t)r.nbt * 16);
     r.scale = pb.add((size_t)r.nbt * 16);
@@ -321,6 +327,21 @@ MfmaRef pack_mfma8(PackBuf& pb, const float* blob, const ConvShape& s, int has_s
         psc[nc] = mx > 0.f ? mx / 448.f : 1.f;
     }
     uint8_t* pw = reinterpret_cast<uint8_t*>(pb.data.data() + r.w);
+    if (k128)
+        for (int st = 0; st < 5; ++st)
+            for (int nb = 0; nb < r.nbt; ++nb)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int j = 0; j < 32; ++j) {
+                        const int kk = lane >> 4, nn = lane & 15;
+                        const int tap = 2 * st + (kk >> 1);
+                        const int k = 32 * (kk & 1) + j;
+                        const int nc = nb * 16 + nn;
+                        float v = 0.f;
+                        if (tap < 9 && nc < s.cout)
+                            v = W[((long long)perm_col(nc, C, lstm) * cin_total + has_sym + k) * 9 + tap] / psc[nc];
+                        pw[(((size_t)st * r.nbt + nb) * 64 + lane) * 32 + j] = host_f2e4m3(v);
+                    }
+    else
     for (int tap = 0; tap < 9; ++tap)
         for (int cc = 0; cc < CC; ++cc)
             for (int nb = 0; nb < r.nbt; ++nb)

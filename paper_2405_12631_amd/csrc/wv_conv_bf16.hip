@@ -12,12 +12,16 @@
 // into registers one tap ahead.  Activations in and out are BF16 (NHWC), the
 // LSTM cell state, every epilogue and the mixture parameters are FP32.
 //
-// FP8 form (F8): the same tiling on v_mfma_f32_16x16x32_fp8_fp8, one 8-byte
-// fragment (8 channels) per lane, activations stored as e4m3 bytes, weights
+// FP8 form (F8): the same tiling, activations stored as e4m3 bytes, weights
 // e4m3 with one FP32 scale per output channel applied to the accumulator
-// before the bias.  The symbol channel keeps its BF16 MFMA chunk (its weights
-// are packed divided by the channel scale), so symbols up to the int16 range
-// stay exact.
+// before the bias.  With 64 input channels and no symbol channel one K step of
+// v_mfma_scale_f32_16x16x128_f8f6f4 (unit block scales) covers two taps: lane
+// group g = 0..3 holds tap 2s + g/2, channels 32 (g % 2) .. + 31 (32 bytes per
+// lane), so nine taps take five steps (the tenth tap is zero) at twice the
+// rate of v_mfma_f32_16x16x32_fp8_fp8, which the other layers keep (one
+// 8-byte fragment of 8 channels per lane).  The symbol channel keeps its BF16
+// MFMA chunk (its weights are packed divided by the channel scale), so symbols
+// up to the int16 range stay exact.
 #include "wv_device.h"
 #include "wv_internal.h"
 
@@ -26,6 +30,9 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int intx8 __attribute__((ext_vector_type(8)));
+
+typedef int intx4 __attribute__((ext_vector_type(4)));
 
 constexpr int TH = 16;
 constexpr int TW = 16;
@@ -46,6 +53,17 @@ __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf1
 __device__ __forceinline__ uint8_t f2e4m3(float f) {
     f = fminf(fmaxf(f, -448.f), 448.f);
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(f, 0.f, 0, false) & 0xff);
+}
+
+// One lane's K = 128 operand (32 e4m3 bytes) from two aligned 16-byte loads.
+__device__ __forceinline__ intx8 load32(const uint8_t* p) {
+    const intx4* q = reinterpret_cast<const intx4*>(p);
+    return __builtin_shufflevector(q[0], q[1], 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__device__ __forceinline__ floatx4 mfma_f8k128(const intx8& a, const intx8& b, const floatx4& c) {
+    // formats 0/0: e4m3 A and B; block scales 0x7f = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
 }
 
 template <bool F8>
@@ -69,12 +87,18 @@ template <int CIN, int NB, bool SYM, int MODE, bool F8>
 __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvArgs& a, const int tile_idx,
                                                const int ycol) {
     using FragT = typename Frag<F8>::T;
+    // Two taps per K = 128 step (see above) for the 64-channel step-stack layers without the
+    // symbol channel (with it, or the ConvLSTM's 256 gate columns, the larger operands leave
+    // the persistent form too few registers).  The weight packer applies the same rule.
+    constexpr bool K128 = F8 && CIN == 64 && !SYM && MODE != CONV_LSTM;
     constexpr int ES = F8 ? 1 : 2;              // bytes per activation element
     constexpr int FB = 8 * ES;                  // bytes per operand fragment (8 K values)
-    constexpr int STRIDE = CIN * ES + 8 * ES;   // bytes per halo position (conflict-free reads)
-    constexpr int CC = CIN / 32;                // 32-channel K chunks per tap
-    constexpr int BU = FB * 64 / 16;            // uint4 per (chunk, 16-column block) of B
-    constexpr int BV = CC * NB * BU;            // uint4 of B per tap for this workgroup
+    // bytes per halo position (conflict-free reads; 16-byte aligned for the 32-byte K128 reads)
+    constexpr int STRIDE = K128 ? CIN + 16 : CIN * ES + 8 * ES;
+    constexpr int CC = K128 ? 1 : CIN / 32;     // K chunks per staged B slice (a tap, or a K128 step)
+    constexpr int BU = K128 ? 128 : FB * 64 / 16;   // uint4 per (chunk, 16-column block) of B
+    constexpr int BV = CC * NB * BU;            // uint4 of B per tap (K128: per step) for this workgroup
+    constexpr int NSTEP = K128 ? 5 : 9;         // staged B slices: taps, or K128 steps
     constexpr int BPT = (BV + 255) / 256;
     constexpr int MB = (MODE == CONV_HEAD) ? 2 : 4;   // head: only the rows of its step's parity
     constexpr int OS = NB * 16 * ES + 16;       // bytes per position of the staged output tile
@@ -196,6 +220,35 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     // are read while this step's MFMAs run (the halo is not written in the loop,
     // so only the B slices need the per-tap barrier).  Fully unrolled so that the
     // fragment double buffer stays in registers.
+  if constexpr (K128) {
+    // Step s: lane group kk reads tap 2 s + kk / 2, channels 32 (kk % 2) .. + 31 of its position.
+    const intx8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < NSTEP; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < NSTEP) {
+            WV_LOAD_B(st + 1)
+        }
+        const uint8_t* wb = reinterpret_cast<const uint8_t*>(lds_w[buf]);
+        intx8 bv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = load32(wb + (nb * BU + 2 * lane) * 16);
+        // Lane group kk: tap 2 st + kk / 2 (tap 9 is zero: read tap 8, then select zero).
+        const int tp = 2 * st + (kk >> 1);
+        const int tpc = tp < 9 ? tp : 8;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            intx8 av = load32(lds_in + ((row_of(mb) + tpc / 3) * HWD + m + tpc % 3) * STRIDE + 32 * (kk & 1));
+            av = tp < 9 ? av : zero8;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_f8k128(av, bv[nb], acc[mb][nb]);
+        }
+        if (st + 1 < NSTEP) {
+            WV_STORE_B(buf ^ 1)   // the other buffer was last read one step ago
+            __syncthreads();
+        }
+    }
+  } else {
     FragT afr[2][MB];
 #define WV_LOAD_A(dst, tp, ccv)                                                                      \
     _Pragma("unroll") for (int mb_ = 0; mb_ < MB; ++mb_) dst[mb_] = *reinterpret_cast<const FragT*>( \
@@ -232,6 +285,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         }
     }
 #undef WV_LOAD_A
+  }
 #undef WV_LOAD_B
 #undef WV_STORE_B
     if (SYM) {
