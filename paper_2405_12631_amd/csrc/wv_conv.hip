@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             if (idx_ < BV4) {                                                                      \
                 const int cb_ = idx_ / (NB * 64);                                                  \
                 const int rem_ = idx_ - cb_ * (NB * 64);                                           \
-                const float4 v_ = wt_[((long long)cb_ * (Lq).nbt + (ycq) * NB + (rem_ >> 6)) * 64 + (rem_ & 63)]; \
+                const float4 v_ = ld_g(wt_ + ((long long)cb_ * (Lq).nbt + (ycq) * NB + (rem_ >> 6)) * 64 + (rem_ & 63)); \
                 if (k_ == 0) b0 = v_; else if (k_ == 1) b1 = v_; else if (k_ == 2) b2 = v_; else b3 = v_; \
             }                                                                                      \
         }                                                                                          \
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         const int c_ = (P).c0 + (pos_ - hy_ * HALO_W) - 1;                                         \
         hv[k] = make_float4(0.f, 0.f, 0.f, 0.f);                                                   \
         if (idx_ < HALO * V && (A).in && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w)            \
-            hv[k] = *reinterpret_cast<const float4*>(                                              \
+            hv[k] = ld_g(reinterpret_cast<const float4*>(                                          \
                 (A).in + (long long)(P).n * (A).in_ps +                                            \
-                ((long long)(r_ >> (A).in_up) * ((A).w >> (A).in_up) + (c_ >> (A).in_up)) * CIN + c4_ * 4); \
+                ((long long)(r_ >> (A).in_up) * ((A).w >> (A).in_up) + (c_ >> (A).in_up)) * CIN + c4_ * 4)); \
     }
 #define WV_LOAD_S(A, Lq, P)                                                                        \
     if constexpr (SYM) {                                                                           \
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             float v_ = 0.f;                                                                        \
             if (pos_ < HALO && sp_ && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w &&             \
                 (2 * (r_ & 1) + (c_ & 1)) < (A).sym_step)                                          \
-                v_ = (float)sp_[(long long)(r_ >> (A).sym_up) * ws_ + (c_ >> (A).sym_up)];          \
+                v_ = (float)gmem(sp_)[(long long)(r_ >> (A).sym_up) * ws_ + (c_ >> (A).sym_up)];    \
             sv[k_] = v_;                                                                           \
         }                                                                                          \
         _Pragma("unroll") for (int k_ = 0; k_ < NWS; ++k_) {                                       \
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             if (idx_ < 3 * NB * 64) {                                                              \
                 const int chunk_ = idx_ / (NB * 64);                                               \
                 const int rem_ = idx_ - chunk_ * (NB * 64);                                        \
-                wsv[k_] = (Lq).wsym[((long long)chunk_ * (Lq).nbt + (P).ycol * NB) * 64 + rem_];   \
+                wsv[k_] = gmem((Lq).wsym)[((long long)chunk_ * (Lq).nbt + (P).ycol * NB) * 64 + rem_]; \
             }                                                                                      \
         }                                                                                          \
     }
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const float b = L.bias[(nblk0 + nb) * 16 + col];
+                const float b = gmem(L.bias)[(nblk0 + nb) * 16 + col];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = acc[mb][nb][i] + b;
@@ -312,21 +312,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
                                     nblk0 * 16 + c4 * 4;
                 float4 v = *reinterpret_cast<const float4*>(lds_in + pos * OS + c4 * 4);
                 if (MODE == CONV_RES) {
-                    const float4 k = *reinterpret_cast<const float4*>(a.skip + o);
+                    const float4 k = ld_g(reinterpret_cast<const float4*>(a.skip + o));
                     v = make_float4(v.x + k.x, v.y + k.y, v.z + k.z, v.w + k.w);
                 }
-                *reinterpret_cast<float4*>(a.out + o) = v;
+                st_g(reinterpret_cast<float4*>(a.out + o), v);
             }
         }
     } else if constexpr (MODE == CONV_LSTM) {
         // Block nb of this workgroup is gate nb (input, forget, cell, output)
         // of channels 16*ycol .. +15 (the packer orders the columns so).
         const int ch = ycol * 16 + col;
-        const float bi = L.bias[(nblk0 + 0) * 16 + col];
-        const float bf = L.bias[(nblk0 + 1) * 16 + col];
-        const float bg = L.bias[(nblk0 + 2) * 16 + col];
-        const float bo = L.bias[(nblk0 + 3) * 16 + col];
+        const auto bias = gmem(L.bias);
+        const float bi = bias[(nblk0 + 0) * 16 + col];
+        const float bf = bias[(nblk0 + 1) * 16 + col];
+        const float bg = bias[(nblk0 + 2) * 16 + col];
+        const float bo = bias[(nblk0 + 3) * 16 + col];
         const int wp = a.w >> a.cprev_up;
+        // All of this lane's previous cell states first (one wait for all of them;
+        // c_prev and c_out are different buffers).
+        float cp[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = r0 + row0 + mb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = c0 + rowq + i;
+                cp[mb][i] = 0.f;
+                if (a.c_prev && r < a.h && c < a.w)
+                    cp[mb][i] = gmem(a.c_prev)[(long long)n * a.cprev_ps +
+                                               ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
+            }
+        }
+        const auto c_out = gmem(a.c_out);
+        const auto h_out = gmem(a.h_out);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int r = r0 + row0 + mb;
@@ -334,27 +352,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             for (int i = 0; i < 4; ++i) {
                 const int c = c0 + rowq + i;
                 if (r < a.h && c < a.w) {
-                    float cp = 0.f;
-                    if (a.c_prev)
-                        cp = a.c_prev[(long long)n * a.cprev_ps +
-                                      ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C +
-                                      ch];
                     const float gi = sigmoid_fast(acc[mb][0][i] + bi);
                     const float gf = sigmoid_fast(acc[mb][1][i] + bf);
                     const float gg = tanh_fast(acc[mb][2][i] + bg);
                     const float go = sigmoid_fast(acc[mb][3][i] + bo);
-                    const float cn = gf * cp + gi * gg;
+                    const float cn = gf * cp[mb][i] + gi * gg;
                     const float hn = go * tanh_fast(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
-                    a.c_out[o] = cn;
-                    a.h_out[o] = hn;
+                    c_out[o] = cn;
+                    h_out[o] = hn;
                 }
             }
         }
     } else {  // CONV_HEAD: raw 3K outputs of the coded row of each wave -> LDS -> step-g positions
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            lds_head[(wave * TILE_W + rowq + i) * 17 + col] = acc[0][0][i] + L.bias[col];
+            lds_head[(wave * TILE_W + rowq + i) * 17 + col] = acc[0][0][i] + gmem(L.bias)[col];
         __syncthreads();
         if (tid < 4 * TILE_W) {
             const int wv = tid / TILE_W;
@@ -368,7 +381,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
                 const int hg = (a.h - gr + 1) >> 1;
                 const long long gi = (long long)(r >> 1) * wg + (c >> 1);
                 float* o = a.params + ((long long)n * hg * wg + gi) * 3 * K;
-                mixture_head(v, K, a.sigma_min, o);
+                mixture_head(v, K, a.sigma_min, gmem(o));
             }
         }
     }

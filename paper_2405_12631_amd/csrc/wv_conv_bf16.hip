@@ -139,8 +139,8 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 #define WV_LOAD_B(tp)                                       \
     {                                                       \
         const uint4* wt_ = wg + (long long)(tp) * btap;     \
-        b0 = wt_[bo0];                                      \
-        if (BPT > 1) b1 = wt_[bo1];                         \
+        b0 = ld_g(wt_ + bo0);                               \
+        if (BPT > 1) b1 = ld_g(wt_ + bo1);                  \
     }
 #define WV_STORE_B(buf)                                                        \
     {                                                                          \
@@ -166,8 +166,8 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
             const int c = c0 + (pos - hy * HWD) - 1;
             hv[k] = make_uint4(0, 0, 0, 0);
             if (idx < HALO * V && inp && r >= 0 && r < a.h && c >= 0 && c < a.w)
-                hv[k] = *reinterpret_cast<const uint4*>(
-                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN * ES + c16 * 16);
+                hv[k] = ld_g(reinterpret_cast<const uint4*>(
+                    inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN * ES + c16 * 16));
         }
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
@@ -194,12 +194,12 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                 float v = 0.f;
                 if (sp && r >= 0 && r < a.h && c >= 0 && c < a.w &&
                     (2 * (r & 1) + (c & 1)) < a.sym_step)
-                    v = (float)sp[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
+                    v = (float)gmem(sp)[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
                 lds_s[pos] = f2bf(v);   // |symbol| <= 256 is exact in BF16
             }
             const uint4* wsg = reinterpret_cast<const uint4*>(L.wsym);
             for (int idx = tid; idx < NB * 64; idx += 256)
-                lds_ws[idx] = wsg[(long long)nblk0 * 64 + idx];
+                lds_ws[idx] = ld_g(wsg + (long long)nblk0 * 64 + idx);
         }
     }
     WV_STORE_B(0)
@@ -312,7 +312,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     // FP8: the accumulator of packed column nc is scaled by L.scale[nc] before the bias.
     float csc[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) csc[nb] = F8 ? L.scale[(nblk0 + nb) * 16 + col] : 1.f;
+    for (int nb = 0; nb < NB; ++nb) csc[nb] = F8 ? gmem(L.scale)[(nblk0 + nb) * 16 + col] : 1.f;
     if constexpr (MODE == CONV_RELU || MODE == CONV_TANH) {
         // Stage the output tile [256 positions][16 NB channels] in LDS (reusing the
         // halo buffer), then write 16-byte chunks: full, coalesced lines.
@@ -322,7 +322,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                const float b = L.bias[(nblk0 + nb) * 16 + col];
+                const float b = gmem(L.bias)[(nblk0 + nb) * 16 + col];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     float v = F8 ? fmaf(acc[mb][nb][i], csc[nb], b) : acc[mb][nb][i] + b;
@@ -343,17 +343,35 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
             const int r = r0 + pos / TW;
             const int c = c0 + pos % TW;
             if (r < a.h && c < a.w && (nblk0 * 16 + c16 * 16 / ES) < L.cout)
-                *reinterpret_cast<uint4*>(outp + ((long long)n * a.out_ps +
-                                                  ((long long)r * a.w + c) * a.out_cs + nblk0 * 16) * ES +
-                                          c16 * 16) = *reinterpret_cast<const uint4*>(lds_in + pos * OS + c16 * 16);
+                st_g(reinterpret_cast<uint4*>(outp + ((long long)n * a.out_ps +
+                                                      ((long long)r * a.w + c) * a.out_cs + nblk0 * 16) * ES +
+                                              c16 * 16),
+                     *reinterpret_cast<const uint4*>(lds_in + pos * OS + c16 * 16));
         }
     } else if constexpr (MODE == CONV_LSTM) {
         const int ch = ycol * 16 + col;
-        const float bi = L.bias[(nblk0 + 0) * 16 + col];
-        const float bf = L.bias[(nblk0 + 1) * 16 + col];
-        const float bg = L.bias[(nblk0 + 2) * 16 + col];
-        const float bo = L.bias[(nblk0 + 3) * 16 + col];
+        const auto bias = gmem(L.bias);
+        const float bi = bias[(nblk0 + 0) * 16 + col];
+        const float bf = bias[(nblk0 + 1) * 16 + col];
+        const float bg = bias[(nblk0 + 2) * 16 + col];
+        const float bo = bias[(nblk0 + 3) * 16 + col];
         const int wp = a.w >> a.cprev_up;
+        // All of this lane's previous cell states first (one wait for all of them, not one per
+        // position; c_prev and c_out are different buffers).
+        float cp[MB][4];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int r = r0 + row_of(mb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int c = c0 + rowq + i;
+                cp[mb][i] = 0.f;
+                if (a.c_prev && r < a.h && c < a.w)
+                    cp[mb][i] = gmem(a.c_prev)[(long long)n * a.cprev_ps +
+                                               ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
+            }
+        }
+        const auto c_out = gmem(a.c_out);
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             const int r = r0 + row_of(mb);
@@ -361,22 +379,18 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
             for (int i = 0; i < 4; ++i) {
                 const int c = c0 + rowq + i;
                 if (r < a.h && c < a.w) {
-                    float cp = 0.f;
-                    if (a.c_prev)
-                        cp = a.c_prev[(long long)n * a.cprev_ps +
-                                      ((long long)(r >> a.cprev_up) * wp + (c >> a.cprev_up)) * a.C + ch];
                     const float gi = sigmoid_fast(fmaf(acc[mb][0][i], csc[0], bi));
                     const float gf = sigmoid_fast(fmaf(acc[mb][1][i], csc[1 % NB], bf));
                     const float gg = tanh_fast(fmaf(acc[mb][2][i], csc[2 % NB], bg));
                     const float go = sigmoid_fast(fmaf(acc[mb][3][i], csc[3 % NB], bo));
-                    const float cn = gf * cp + gi * gg;
+                    const float cn = gf * cp[mb][i] + gi * gg;
                     const float hn = go * tanh_fast(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
-                    a.c_out[o] = cn;
+                    c_out[o] = cn;
                     if constexpr (F8)
-                        reinterpret_cast<uint8_t*>(a.h16_out)[o] = f2e4m3(hn);
+                        gmem(reinterpret_cast<uint8_t*>(a.h16_out))[o] = f2e4m3(hn);
                     else
-                        a.h16_out[o] = f2bf(hn);
+                        gmem(a.h16_out)[o] = f2bf(hn);
                 }
             }
         }
@@ -386,7 +400,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 lds_head[((wave * 2 + mb) * TW + rowq + i) * 17 + col] =
-                    F8 ? fmaf(acc[mb][0][i], csc[0], L.bias[col]) : acc[mb][0][i] + L.bias[col];
+                    F8 ? fmaf(acc[mb][0][i], csc[0], gmem(L.bias)[col]) : acc[mb][0][i] + gmem(L.bias)[col];
         __syncthreads();
         if (tid < 8 * TW) {
             const int rr = tid / TW;                       // 0..7: wave rr/2, block rr%2
@@ -400,7 +414,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                 const int hg = (a.h - gr + 1) >> 1;
                 const long long gi = (long long)(r >> 1) * wg2 + (c >> 1);
                 float* o = a.params + ((long long)n * hg * wg2 + gi) * 3 * K;
-                mixture_head(v, K, a.sigma_min, o);
+                mixture_head(v, K, a.sigma_min, gmem(o));
             }
         }
     }

@@ -10,6 +10,28 @@
 
 namespace wv {
 
+// The same pointer in the global address space, so that accesses through it
+// compile to global_* instructions.  A pointer read from memory (a segment
+// descriptor) is otherwise generic and its accesses flat_*, which count against
+// the LDS wait counter as well: every wait for an LDS read in an MFMA loop would
+// then also wait for the HBM loads in flight.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+// Loads and stores of the HIP vector structs (uint4, float4, ...) through such a
+// pointer, moved as a plain vector of 32-bit words.
+template <class T>
+__device__ __forceinline__ T ld_g(const T* p) {
+    typedef uint32_t W __attribute__((ext_vector_type(sizeof(T) / 4)));
+    return __builtin_bit_cast(T, *gmem(reinterpret_cast<const W*>(p)));
+}
+template <class T>
+__device__ __forceinline__ void st_g(T* p, const T& v) {
+    typedef uint32_t W __attribute__((ext_vector_type(sizeof(T) / 4)));
+    *gmem(reinterpret_cast<W*>(p)) = __builtin_bit_cast(W, v);
+}
+
 // tanh x = 1 - 2 / (e^{2x} + 1) and the logistic 1 / (1 + e^{-x}) from the
 // hardware exponential and reciprocal: absolute error about 1e-7, the exact
 // limits for large |x| (e^{2x} overflowing to inf gives 1, underflowing to 0
@@ -21,7 +43,8 @@ __device__ __forceinline__ float sigmoid_fast(float x) { return __builtin_amdgcn
 
 // Mixture head (Sec. 3.1 / 3.2 entropy parameters): raw 3K values ->
 // w = softmax(v[0:K]), mu = v[K:2K], sigma = max(softplus(v[2K:3K]), sigma_min).
-__device__ __forceinline__ void mixture_head(const float* v, int K, float sigma_min, float* o) {
+template <class OutPtr>
+__device__ __forceinline__ void mixture_head(const float* v, int K, float sigma_min, OutPtr o) {
     float mx = v[0];
     for (int k = 1; k < K; ++k) mx = fmaxf(mx, v[k]);
     float e[4];
