@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     const int kk = lane >> 4;
 
     float4 hv[NH];
-    float sv[NS];
+    int16_t sraw[NS];
+    bool sok[NS];
     float wsv[NWS];
     float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0, b3 = b0;
     // B fragments of tap tp for blocks [ycq NB, ycq NB + NB): global [tap][cb][nbt][64][4], LDS [cb][nb][64].
@@ -141,18 +142,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
     }
 #define WV_LOAD_S(A, Lq, P)                                                                        \
     if constexpr (SYM) {                                                                           \
-        const int16_t* sp_ = (A).sym ? (A).sym + (long long)(P).n * (A).sym_ps : nullptr;           \
+        /* unconditional loads (clamped address; without symbols a valid dummy one, the first    \
+           weight), masked when stored: a load under a branch that converts its result waits    \
+           inside the branch, for every load in flight */                                        \
+        const bool has_ = (A).sym != nullptr;                                                      \
+        const auto sp_ = gmem(has_ ? (A).sym + (long long)(P).n * (A).sym_ps                        \
+                                   : reinterpret_cast<const int16_t*>((Lq).w));                    \
         const int ws_ = (A).w >> (A).sym_up;                                                       \
         _Pragma("unroll") for (int k_ = 0; k_ < NS; ++k_) {                                        \
             const int pos_ = tid + k_ * 256;                                                       \
             const int hy_ = pos_ / HALO_W;                                                         \
             const int r_ = (P).r0 + hy_ - 1;                                                       \
             const int c_ = (P).c0 + (pos_ - hy_ * HALO_W) - 1;                                     \
-            float v_ = 0.f;                                                                        \
-            if (pos_ < HALO && sp_ && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w &&             \
-                (2 * (r_ & 1) + (c_ & 1)) < (A).sym_step)                                          \
-                v_ = (float)gmem(sp_)[(long long)(r_ >> (A).sym_up) * ws_ + (c_ >> (A).sym_up)];    \
-            sv[k_] = v_;                                                                           \
+            sok[k_] = has_ && pos_ < HALO && r_ >= 0 && r_ < (A).h && c_ >= 0 && c_ < (A).w &&      \
+                      (2 * (r_ & 1) + (c_ & 1)) < (A).sym_step;                                    \
+            const int rc_ = min(max(r_, 0), (A).h - 1);                                            \
+            const int cc_ = min(max(c_, 0), (A).w - 1);                                            \
+            sraw[k_] = sp_[has_ ? (long long)(rc_ >> (A).sym_up) * ws_ + (cc_ >> (A).sym_up) : 0ll]; \
         }                                                                                          \
         _Pragma("unroll") for (int k_ = 0; k_ < NWS; ++k_) {                                       \
             const int idx_ = tid + k_ * 256;                                                       \
@@ -196,7 +202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         if constexpr (SYM) {
 #pragma unroll
             for (int k = 0; k < NS; ++k)
-                if (tid + k * 256 < HALO) lds_s[tid + k * 256] = sv[k];
+                if (tid + k * 256 < HALO) lds_s[tid + k * 256] = sok[k] ? (float)sraw[k] : 0.f;
 #pragma unroll
             for (int k = 0; k < NWS; ++k)
                 if (tid + k * 256 < 3 * NB * 64) lds_ws[tid + k * 256] = wsv[k];

@@ -100,6 +100,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     constexpr int BV = CC * NB * BU;            // uint4 of B per tap (K128: per step) for this workgroup
     constexpr int NSTEP = K128 ? 5 : 9;         // staged B slices: taps, or K128 steps
     constexpr int BPT = (BV + 255) / 256;
+    constexpr int NSY = (HALO + 255) / 256;     // symbol positions per thread
     constexpr int MB = (MODE == CONV_HEAD) ? 2 : 4;   // head: only the rows of its step's parity
     constexpr int OS = NB * 16 * ES + 16;       // bytes per position of the staged output tile
     static_assert(BPT <= 2, "B slice too large");
@@ -169,37 +170,54 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                 hv[k] = ld_g(reinterpret_cast<const uint4*>(
                     inp + ((long long)(r >> a.in_up) * win + (c >> a.in_up)) * CIN * ES + c16 * 16));
         }
+        auto store_halo = [&]() {
 #pragma unroll
-        for (int k = 0; k < NH; ++k) {
-            const int idx = tid + k * 256;
-            if (idx < HALO * V) {
-                const int pos = idx / V;
-                uint8_t* dst = lds_in + pos * STRIDE + (idx - pos * V) * 16;
-                if constexpr (F8) {   // 8-byte aligned positions
-                    reinterpret_cast<uint2*>(dst)[0] = make_uint2(hv[k].x, hv[k].y);
-                    reinterpret_cast<uint2*>(dst)[1] = make_uint2(hv[k].z, hv[k].w);
-                } else {
-                    *reinterpret_cast<uint4*>(dst) = hv[k];
+            for (int k = 0; k < NH; ++k) {
+                const int idx = tid + k * 256;
+                if (idx < HALO * V) {
+                    const int pos = idx / V;
+                    uint8_t* dst = lds_in + pos * STRIDE + (idx - pos * V) * 16;
+                    if constexpr (F8) {   // 8-byte aligned positions
+                        reinterpret_cast<uint2*>(dst)[0] = make_uint2(hv[k].x, hv[k].y);
+                        reinterpret_cast<uint2*>(dst)[1] = make_uint2(hv[k].z, hv[k].w);
+                    } else {
+                        *reinterpret_cast<uint4*>(dst) = hv[k];
+                    }
                 }
             }
-        }
-        if (SYM) {
-            const int16_t* sp = a.sym ? a.sym + (long long)n * a.sym_ps : nullptr;
+        };
+        if constexpr (SYM) {
+            // Symbols of the halo (masked by coding step) and the symbol-channel weights: issued
+            // right behind the halo loads, so that one wait covers all of them.
+            // The loads are unconditional, from a clamped address (or, without symbols, from a
+            // valid dummy one: the first weight), and the mask is applied after the wait: a
+            // load under a branch whose result is converted there waits inside the branch.
+            const bool has = a.sym != nullptr;
+            const auto sp = gmem(has ? a.sym + (long long)n * a.sym_ps : reinterpret_cast<const int16_t*>(L.w));
             const int ws = a.w >> a.sym_up;
-            for (int pos = tid; pos < HALO; pos += 256) {
+            int16_t sraw[NSY];
+            bool sok[NSY];
+#pragma unroll
+            for (int k = 0; k < NSY; ++k) {
+                const int pos = tid + k * 256;
                 const int hy = pos / HWD;
-                const int hx = pos - hy * HWD;
                 const int r = r0 + hy - 1;
-                const int c = c0 + hx - 1;
-                float v = 0.f;
-                if (sp && r >= 0 && r < a.h && c >= 0 && c < a.w &&
-                    (2 * (r & 1) + (c & 1)) < a.sym_step)
-                    v = (float)gmem(sp)[(long long)(r >> a.sym_up) * ws + (c >> a.sym_up)];
-                lds_s[pos] = f2bf(v);   // |symbol| <= 256 is exact in BF16
+                const int c = c0 + (pos - hy * HWD) - 1;
+                sok[k] = has && pos < HALO && r >= 0 && r < a.h && c >= 0 && c < a.w &&
+                         (2 * (r & 1) + (c & 1)) < a.sym_step;
+                const int rc = min(max(r, 0), a.h - 1);
+                const int cc = min(max(c, 0), a.w - 1);
+                sraw[k] = sp[has ? (long long)(rc >> a.sym_up) * ws + (cc >> a.sym_up) : 0ll];
             }
-            const uint4* wsg = reinterpret_cast<const uint4*>(L.wsym);
-            for (int idx = tid; idx < NB * 64; idx += 256)
-                lds_ws[idx] = ld_g(wsg + (long long)nblk0 * 64 + idx);
+            uint4 wsv = make_uint4(0, 0, 0, 0);
+            if (tid < NB * 64) wsv = ld_g(reinterpret_cast<const uint4*>(L.wsym) + (long long)nblk0 * 64 + tid);
+            store_halo();
+#pragma unroll
+            for (int k = 0; k < NSY; ++k)   // |symbol| <= 256: exact in BF16
+                if (tid + k * 256 < HALO) lds_s[tid + k * 256] = f2bf(sok[k] ? (float)sraw[k] : 0.f);
+            if (tid < NB * 64) lds_ws[tid] = wsv;
+        } else {
+            store_halo();
         }
     }
     WV_STORE_B(0)
@@ -228,6 +246,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         const int buf = st & 1;
         if (st + 1 < NSTEP) {
             WV_LOAD_B(st + 1)
+            __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of this step's MFMAs
         }
         const uint8_t* wb = reinterpret_cast<const uint8_t*>(lds_w[buf]);
         intx8 bv[NB];
@@ -259,6 +278,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         const int buf = tap & 1;
         if (tap < 8) {
             WV_LOAD_B(tap + 1)
+            __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of this tap's MFMAs
         }
         const FragT* wb = reinterpret_cast<const FragT*>(lds_w[buf]);
         FragT bv[CC][NB];
