@@ -102,6 +102,8 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
         b1s[i] = L1.bias[i];
         b2s[i] = L2.bias[i];
     }
+    const float b3 = L3.bias[0];
+    constexpr int NTASK = 2 * OH * OW / NT;   // layer-3 rounds (two threads per output)
 
   for (int t = blockIdx.x; t < total; t += gridDim.x) {
     const Tile T = tile_of(t);
@@ -111,6 +113,17 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
     for (int k = 0; k < NZ; ++k)
         if (tid + k * NT < ZH * ZW) zs[tid + k * NT] = zv_next[k];
     __syncthreads();
+    // The array this tile updates, one value per output of this thread's layer-3 rounds: read
+    // now, used after layer 3.
+    float apre[NTASK];
+#pragma unroll
+    for (int j = 0; j < NTASK; ++j) {
+        const int o = (j * NT + tid) >> 1;
+        const int r = r0 + o / OW, c = c0 + o % OW;
+        apre[j] = 0.f;
+        if (((j * NT + tid) & 1) == 0 && r < h && c < w)
+            apre[j] = A.p[(long long)n * A.ps + (long long)r * A.rs + (long long)c * A.cs];
+    }
 
     // layer 1 on the (OH+4) x (OW+4) region: tanh(b1 + sum_tap w1 z), zero outside the array
     for (int i = tid; i < AH * AW * (C / 4); i += NT) {
@@ -203,8 +216,8 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
 
     // layer 3 and the lifting update: two threads per output, halves of the channels
 #pragma unroll
-    for (int task0 = 0; task0 < 2 * OH * OW; task0 += NT) {
-        const int task = task0 + tid;
+    for (int j = 0; j < NTASK; ++j) {
+        const int task = j * NT + tid;
         const int o = task >> 1;
         const int half = task & 1;
         const int oy = o / OW, ox = o % OW;
@@ -226,12 +239,11 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
         const float other = __shfl_xor(s, 1);
         const int r = r0 + oy, c = c0 + ox;
         if (half == 0 && r < h && c < w) {
-            const float v = L3.bias[0] + (s + other);
+            const float v = b3 + (s + other);
             const float zz = zs[(oy + 3) * ZW + ox + 3];
             float f = predict ? zz + v : 0.5f * zz + v;
             if (lift_int) f = rintf(f);
-            const float av = A.p[(long long)n * A.ps + (long long)r * A.rs + (long long)c * A.cs];
-            out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = av + sign * f;
+            out.p[(long long)n * out.ps + (long long)r * out.rs + (long long)c * out.cs] = apre[j] + sign * f;
         }
     }
   }
