@@ -8,8 +8,8 @@
 // limit.  The tile is therefore taller: a workgroup owns 16 x 16 positions,
 // each of its 4 waves 4 rows x (16 NB) channels (16 accumulators for NB = 4).
 // A fragments: one 16-byte LDS read = 8 channels of one position per lane;
-// B fragments: per-tap weight slices staged in LDS, double buffered, fetched
-// into registers one tap ahead.  Activations in and out are BF16 (NHWC), the
+// B fragments: per-tap weight slices staged in LDS in three buffers, read from
+// HBM/L2 two taps ahead and stored to LDS one tap ahead.  Activations in and out are BF16 (NHWC), the
 // LSTM cell state, every epilogue and the mixture parameters are FP32.
 //
 // FP8 form (F8): the same tiling, activations stored as e4m3 bytes, weights
@@ -107,7 +107,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     // Input halo; after the MFMA loop it holds the output tile (RELU/TANH epilogue).
     constexpr int LDS_IN = HALO * STRIDE > TH * TW * OS ? HALO * STRIDE : TH * TW * OS;
     __shared__ __attribute__((aligned(16))) uint8_t lds_in[LDS_IN];
-    __shared__ __attribute__((aligned(16))) uint4 lds_w[2][BV];
+    __shared__ __attribute__((aligned(16))) uint4 lds_w[3][BV];
     __shared__ __attribute__((aligned(16))) uint4 lds_ws[SYM ? NB * 64 : 1];
     __shared__ uint16_t lds_s[SYM ? HALO : 1];
     __shared__ float lds_head[MODE == CONV_HEAD ? 8 * TW * 17 : 1];
@@ -136,17 +136,19 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     const long long bo0 = boff_of(0);
     const long long bo1 = BPT > 1 ? boff_of(1) : 0;
     const long long btap = (long long)CC * L.nbt * BU;
-    uint4 b0, b1;
+    // B slice k (a tap, or a K128 step) goes global -> registers (set k % 2) two slices ahead,
+    // registers -> LDS buffer k % 3 one slice ahead.
+    uint4 bq[2][2];
 #define WV_LOAD_B(tp)                                       \
     {                                                       \
         const uint4* wt_ = wg + (long long)(tp) * btap;     \
-        b0 = ld_g(wt_ + bo0);                               \
-        if (BPT > 1) b1 = ld_g(wt_ + bo1);                  \
+        bq[(tp) & 1][0] = ld_g(wt_ + bo0);                  \
+        if (BPT > 1) bq[(tp) & 1][1] = ld_g(wt_ + bo1);     \
     }
-#define WV_STORE_B(buf)                                                        \
-    {                                                                          \
-        if (BV >= 256 || tid < BV) lds_w[buf][tid] = b0;                       \
-        if (BPT > 1 && (BV >= 512 || tid + 256 < BV)) lds_w[buf][tid + 256] = b1; \
+#define WV_STORE_B(tp)                                                                            \
+    {                                                                                             \
+        if (BV >= 256 || tid < BV) lds_w[(tp) % 3][tid] = bq[(tp) & 1][0];                        \
+        if (BPT > 1 && (BV >= 512 || tid + 256 < BV)) lds_w[(tp) % 3][tid + 256] = bq[(tp) & 1][1]; \
     }
     WV_LOAD_B(0)
 
@@ -221,6 +223,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
         }
     }
     WV_STORE_B(0)
+    WV_LOAD_B(1)
     __syncthreads();
 
     floatx4 acc[MB][NB];
@@ -243,12 +246,11 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     const intx8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int st = 0; st < NSTEP; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < NSTEP) {
-            WV_LOAD_B(st + 1)
+        if (st + 2 < NSTEP) {
+            WV_LOAD_B(st + 2)
             __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of this step's MFMAs
         }
-        const uint8_t* wb = reinterpret_cast<const uint8_t*>(lds_w[buf]);
+        const uint8_t* wb = reinterpret_cast<const uint8_t*>(lds_w[st % 3]);
         intx8 bv[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) bv[nb] = load32(wb + (nb * BU + 2 * lane) * 16);
@@ -263,7 +265,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
             for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_f8k128(av, bv[nb], acc[mb][nb]);
         }
         if (st + 1 < NSTEP) {
-            WV_STORE_B(buf ^ 1)   // the other buffer was last read one step ago
+            WV_STORE_B(st + 1)   // buffer (st + 1) % 3 was last read two steps ago
             __syncthreads();
         }
     }
@@ -275,12 +277,11 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
     WV_LOAD_A(afr[0], 0, 0)
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int buf = tap & 1;
-        if (tap < 8) {
-            WV_LOAD_B(tap + 1)
+        if (tap < 7) {
+            WV_LOAD_B(tap + 2)
             __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of this tap's MFMAs
         }
-        const FragT* wb = reinterpret_cast<const FragT*>(lds_w[buf]);
+        const FragT* wb = reinterpret_cast<const FragT*>(lds_w[tap % 3]);
         FragT bv[CC][NB];
 #pragma unroll
         for (int cc = 0; cc < CC; ++cc)
@@ -300,7 +301,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                 for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = mfma_lp<F8>(afr[st & 1][mb], bv[cc][nb], acc[mb][nb]);
         }
         if (tap < 8) {
-            WV_STORE_B(buf ^ 1)   // the other buffer was last read one tap ago
+            WV_STORE_B(tap + 1)   // buffer (tap + 1) % 3 was last read two taps ago
             __syncthreads();
         }
     }
