@@ -39,7 +39,7 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
     constexpr int MB2 = (NP2 + 15) / 16;    // M blocks
     constexpr int CB = C / 16;              // K chunks (16 channels) per tap
     constexpr int NBT = C / 16;             // output blocks of 16
-    constexpr int MBW = (MB2 + NWV - 1) / NWV;   // M blocks per wave (the last ones may be padding)
+    constexpr int MBW = (MB2 + NWV - 1) / NWV;   // most M blocks a wave takes
     static_assert((2 * OH * OW) % NT == 0, "layer 3 takes two threads per output in whole rounds");
     __shared__ float zs[ZH * ZW];
     __shared__ __attribute__((aligned(16))) float act[AH * AW * S1];   // layer 1, then layer 2
@@ -152,13 +152,16 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
     // layer 2 on the (OH+2) x (OW+2) region: MFMA over K = 9 taps x C channels
     const int m = lane & 15;
     const int kk = lane >> 4;
+    // Wave w takes M blocks [mb0, mb0 + mcnt): MB2 split as evenly as whole blocks allow.
+    const int mcnt = MB2 / NWV + (wave < MB2 % NWV ? 1 : 0);
+    const int mb0 = wave * (MB2 / NWV) + (wave < MB2 % NWV ? wave : MB2 % NWV);
     floatx4 acc[MBW][NBT];
     int apos[MBW];
 #pragma unroll
     for (int j = 0; j < MBW; ++j) {
-        const int mb = wave * MBW + j;
+        const int mb = mb0 + j;
         int p = mb * 16 + m;
-        p = p < NP2 ? p : NP2 - 1;                          // dummy rows read a valid position
+        p = p < NP2 && j < mcnt ? p : NP2 - 1;              // dummy rows read a valid position
         apos[j] = (p / BW) * AW + (p % BW);
 #pragma unroll
         for (int nb = 0; nb < NBT; ++nb) acc[j][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -177,7 +180,8 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
 #define WV_STEP(cur, st)                                                                            \
     {                                                                                               \
         if ((st) + 1 < 9 * CB) WV_LOAD_F((cur) ^ 1, ((st) + 1) / CB, ((st) + 1) % CB)                 \
-        _Pragma("unroll") for (int j = 0; j < MBW; ++j) _Pragma("unroll") for (int nb = 0; nb < NBT; ++nb) { \
+        _Pragma("unroll") for (int j = 0; j < MBW; ++j) if (MB2 % NWV == 0 || j < mcnt)             \
+            _Pragma("unroll") for (int nb = 0; nb < NBT; ++nb) {                                    \
             acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].x, bfr[cur][nb].x, acc[j][nb], 0, 0, 0); \
             acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].y, bfr[cur][nb].y, acc[j][nb], 0, 0, 0); \
             acc[j][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[cur][j].z, bfr[cur][nb].z, acc[j][nb], 0, 0, 0); \
@@ -198,7 +202,8 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
     const int rowq = (lane >> 4) * 4;
 #pragma unroll
     for (int j = 0; j < MBW; ++j) {
-        const int mb = wave * MBW + j;
+        if (MB2 % NWV != 0 && j >= mcnt) continue;
+        const int mb = mb0 + j;
 #pragma unroll
         for (int nb = 0; nb < NBT; ++nb) {
             const int ch = nb * 16 + col;
