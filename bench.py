@@ -36,12 +36,12 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X den
 # factors being what each counter reads for a plain 1 GiB device copy; averaged over the 1326
 # launches of six 512x768x3 decodes.  Valid only for the conv sources with these sha256.
 TRAFFIC_SOURCES = {
-    "paper_2405_12631_amd/csrc/wv_conv.hip": "5d304fb56ef2d1a598c543b7131b29868c1c1e90e3e20e895c9a3768591f50d9",
-    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "d3cd3e02c13abd83a72f17ecbb395a5354e78ca4eb8acb29cf34d37fac8dabb5",
-    "paper_2405_12631_amd/csrc/wv_device.h": "b20ce3ff0225e18b14ad70a1560cf9a9bcc2c4b28cfb200f15dd07098e331a8e",
+    "paper_2405_12631_amd/csrc/wv_conv.hip": "3fc89fb6b86d2d4efabb039bf86840ce15ce9481e614399f23447f9a4011711b",
+    "paper_2405_12631_amd/csrc/wv_conv_bf16.hip": "f9f36cf171a443ea6f55eef6fea74f3cacc3a82ddb7a5889d9a4a6a4d7c70fce",
+    "paper_2405_12631_amd/csrc/wv_device.h": "0f2ba9eb94148176d46bbfb80909b1171d4f4d9d20c4230716f14a7d11a2ce3a",
     "paper_2405_12631_amd/csrc/wv_internal.h": "28fe2efef9fdeefc93f7dc93002e459af2d845b0a14881e31cc954149aba3f79",
 }
-TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 49.21e6, "bf16": 25.64e6, "fp8": 14.95e6}
+TRAFFIC_BYTES_PER_LAUNCH = {"fp32": 49.33e6, "bf16": 25.68e6, "fp8": 15.02e6}
 
 
 def measured_traffic(precision):

@@ -12,8 +12,11 @@
 //     (F_j = F_max - ceil(F_max * (1 - C_j)), at least one count below F_max),
 //     so no digits are lost to 1 - tiny rounding to 1;
 //   * a running maximum makes the row non-decreasing.
-// One thread builds one row in LDS; the 64 rows of a workgroup are then
-// written out as one contiguous, coalesced block.
+// A workgroup builds 64 rows in LDS, one thread per row, or (launches too small to
+// fill the GPU, where one thread's 128 serial entries set the time) LPR lanes per
+// row, each a contiguous slice of the entries, the running maximum completed by a
+// prefix maximum over the row's lanes; either way the 64 rows are then written out
+// as one contiguous, coalesced block, and the tables are the same.
 #include "wv_device.h"
 #include "wv_internal.h"
 
@@ -23,26 +26,50 @@ namespace {
 constexpr int ROWS = 64;
 constexpr int MAXE = 256;   // max entries per row (N_s + 1)
 
-template <int K, int DIST>
-__global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, long long n, int smin,
-                                             int nsym, uint16_t* __restrict__ out) {
+template <int K, int DIST, int LPR>
+__global__ __launch_bounds__(ROWS * LPR) void cdf_k(const float* __restrict__ params, long long n, int smin,
+                                                   int nsym, uint16_t* __restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) uint16_t rows[];   // [ROWS][nsym + 1]
-    const int t = threadIdx.x;
+    const int t = threadIdx.x / LPR;   // row of this lane in the block
+    const int sl = threadIdx.x % LPR;  // its slice of the row's entries
     const int E = nsym + 1;
     const long long row0 = (long long)blockIdx.x * ROWS;
     const long long row = row0 + t;
     const int nrows = (int)((n - row0) < ROWS ? (n - row0) : ROWS);
     uint16_t* my = rows + t * E;
+    // entries j = 1 .. nsym - 1 in LPR contiguous slices
+    const int per = (nsym - 1 + LPR - 1) / LPR;
+    const int ja = 1 + sl * per;
+    const int jb = ja + per < nsym ? ja + per : nsym;
+    int F = 0;
     if (row < n) {
         CdfRow<K, DIST> R;
         cdf_setup<K, DIST>(params + row * (3 * K), smin, nsym, R);
-        my[0] = 0;
-        int F = 0;
-        for (int j = 1; j < nsym; ++j) {
+        for (int j = ja; j < jb; ++j) {
             const int Fj = cdf_F<K, DIST>(R, j);
             F = Fj > F ? Fj : F;
-            my[j] = (uint16_t)(j + F);
+            my[j] = (uint16_t)(LPR > 1 ? F : j + F);   // running maximum within the slice
         }
+    }
+    if constexpr (LPR > 1) {
+        // Maximum of F over the slices before this one: inclusive max-scan over the row's
+        // lanes, shifted by one (F >= 0, so 0 is neutral).
+        int incl = F;
+#pragma unroll
+        for (int d = 1; d < LPR; d <<= 1) {
+            const int o = __shfl_up(incl, d, LPR);
+            if (sl >= d) incl = o > incl ? o : incl;
+        }
+        int pre = __shfl_up(incl, 1, LPR);
+        if (sl == 0) pre = 0;
+        if (row < n)
+            for (int j = ja; j < jb; ++j) {
+                const int f = my[j];
+                my[j] = (uint16_t)(j + (f > pre ? f : pre));
+            }
+    }
+    if (row < n && sl == 0) {
+        my[0] = 0;
         my[nsym] = 0;   // 2^16 mod 2^16
     }
     __syncthreads();
@@ -52,9 +79,9 @@ __global__ __launch_bounds__(ROWS) void cdf_k(const float* __restrict__ params, 
     if ((((uintptr_t)dst) & 15) == 0 && (nel & 7) == 0) {
         const uint4* src4 = reinterpret_cast<const uint4*>(rows);
         uint4* dst4 = reinterpret_cast<uint4*>(dst);
-        for (long long i = t; i < nel / 8; i += ROWS) dst4[i] = src4[i];
+        for (long long i = threadIdx.x; i < nel / 8; i += ROWS * LPR) dst4[i] = src4[i];
     } else {
-        for (long long i = t; i < nel; i += ROWS) dst[i] = rows[i];
+        for (long long i = threadIdx.x; i < nel; i += ROWS * LPR) dst[i] = rows[i];
     }
 }
 
@@ -66,10 +93,16 @@ hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smi
     if (nsym + 1 > MAXE || nsym < 2) return hipErrorInvalidValue;
     const unsigned g = (unsigned)((n + ROWS - 1) / ROWS);
     const size_t lds = ((size_t)ROWS * (nsym + 1) * sizeof(uint16_t) + 15) & ~(size_t)15;
-#define WV_CDF_CASE(KK, DD)                                                                   \
-    if (K == KK && dist == DD) {                                                              \
-        hipLaunchKernelGGL((cdf_k<KK, DD>), dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf); \
-        return hipGetLastError();                                                             \
+    // One lane per row once the launch has more than ~4 waves per SIMD of rows; below that
+    // the serial row length sets the time and 4 lanes per row take a quarter of it each.
+    const bool split = n <= 256ll * 1024;
+#define WV_CDF_CASE(KK, DD)                                                                                  \
+    if (K == KK && dist == DD) {                                                                             \
+        if (split)                                                                                           \
+            hipLaunchKernelGGL((cdf_k<KK, DD, 4>), dim3(g), dim3(ROWS * 4), lds, s, params, n, smin, nsym, cdf); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((cdf_k<KK, DD, 1>), dim3(g), dim3(ROWS), lds, s, params, n, smin, nsym, cdf);     \
+        return hipGetLastError();                                                                            \
     }
     WV_CDF_CASE(1, 0) WV_CDF_CASE(2, 0) WV_CDF_CASE(3, 0) WV_CDF_CASE(4, 0)
     WV_CDF_CASE(1, 1) WV_CDF_CASE(2, 1) WV_CDF_CASE(3, 1) WV_CDF_CASE(4, 1)

@@ -96,6 +96,30 @@ def test_cdf_extreme_params():
     assert empty.shape[0] == 0
 
 
+def test_cdf_row_split_forms_bitwise():
+    """Launches of up to 256 Ki rows build each row with 4 lanes (slices of the entries and a
+    prefix maximum), larger ones with one lane per row: identical tables."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    cfg = get_config("gray64")
+    model, _ = model_for(cfg)
+    rng = np.random.default_rng(47)
+    n = 300_000                                  # one lane per row
+    logits = rng.normal(0, 3, (n, 3))
+    w = np.exp(logits - logits.max(1, keepdims=True))
+    w /= w.sum(1, keepdims=True)
+    mu = rng.uniform(-90, 90, (n, 3))
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(200), (n, 3)))
+    prm = torch.from_numpy(np.concatenate([w, mu, sg], 1).astype(np.float32)).cuda()
+    say("cdf rows", n)
+    big = codec.cdf_tables(model, prm).cpu().numpy().view(np.uint16)
+    check_cdf_rows(big[:1000], prm[:1000].cpu().numpy(), cfg)
+    for m in (1, 65, 5000, 262_144):             # four lanes per row
+        say("cdf rows (split)", m)
+        part = codec.cdf_tables(model, prm[:m]).cpu().numpy().view(np.uint16)
+        assert np.array_equal(part, big[:m]), m
+
+
 def test_cdf_trim_matches_oracle_definition():
     need_gpu()
     import ctypes
