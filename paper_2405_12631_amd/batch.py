@@ -172,10 +172,14 @@ def autotune(batch, syms, choices=(1, 2, 4), reps=2, log=None):
     best_tab, best_t = None, run(None)
     if log:
         log(f"autotune: default {best_t * 1e3:.2f} ms")
+    seen = set()
     for lev in range(J, 0, -1):          # coarse levels first: fewest tiles
         for c in choices:
             tab = list(best_tab or [4] * J)
             tab[lev - 1] = c
+            if tuple(tab) in seen:       # measured already (the table being improved)
+                continue
+            seen.add(tuple(tab))
             t = run(tab)
             if log:
                 log(f"autotune: table {tab} {t * 1e3:.2f} ms")
