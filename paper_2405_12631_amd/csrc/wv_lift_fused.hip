@@ -125,27 +125,38 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
             apre[j] = A.p[(long long)n * A.ps + (long long)r * A.rs + (long long)c * A.cs];
     }
 
-    // layer 1 on the (OH+4) x (OW+4) region: tanh(b1 + sum_tap w1 z), zero outside the array
-    for (int i = tid; i < AH * AW * (C / 4); i += NT) {
-        const int pos = i / (C / 4);
-        const int c4 = (i - pos * (C / 4)) * 4;
-        const int ay = pos / AW, ax = pos % AW;
-        const int r = r0 - 2 + ay, c = c0 - 2 + ax;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r >= 0 && r < h && c >= 0 && c < w) {
-            float zv[9];
+    // layer 1 on the (OH+4) x (OW+4) region: tanh(b1 + sum_tap w1 z), zero outside the array.
+    // A thread always takes the same four channels (NT is a multiple of C / 4), so their 36
+    // weights and 4 biases are read from LDS once per tile.
+    static_assert(NT % (C / 4) == 0, "fixed channel group per thread");
+    {
+        const int c4 = (tid % (C / 4)) * 4;
+        float w1r[9][4], b1r[4];
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) zv[tap] = zs[(ay + tap / 3) * ZW + ax + tap % 3];
-            float s[4];
+        for (int j = 0; j < 4; ++j) {
+            b1r[j] = b1s[c4 + j];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                s[j] = b1s[c4 + j];
-#pragma unroll
-                for (int tap = 0; tap < 9; ++tap) s[j] = fmaf(w1s[tap * C + c4 + j], zv[tap], s[j]);
-            }
-            v = make_float4(tanh_fast(s[0]), tanh_fast(s[1]), tanh_fast(s[2]), tanh_fast(s[3]));
+            for (int tap = 0; tap < 9; ++tap) w1r[tap][j] = w1s[tap * C + c4 + j];
         }
-        *reinterpret_cast<float4*>(act + pos * S1 + c4) = v;
+        for (int pos = tid / (C / 4); pos < AH * AW; pos += NT / (C / 4)) {
+            const int ay = pos / AW, ax = pos % AW;
+            const int r = r0 - 2 + ay, c = c0 - 2 + ax;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r >= 0 && r < h && c >= 0 && c < w) {
+                float zv[9];
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) zv[tap] = zs[(ay + tap / 3) * ZW + ax + tap % 3];
+                float s[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    s[j] = b1r[j];
+#pragma unroll
+                    for (int tap = 0; tap < 9; ++tap) s[j] = fmaf(w1r[tap][j], zv[tap], s[j]);
+                }
+                v = make_float4(tanh_fast(s[0]), tanh_fast(s[1]), tanh_fast(s[2]), tanh_fast(s[3]));
+            }
+            *reinterpret_cast<float4*>(act + pos * S1 + c4) = v;
+        }
     }
     __syncthreads();
 
