@@ -120,6 +120,32 @@ def test_cdf_row_split_forms_bitwise():
         assert np.array_equal(part, big[:m]), m
 
 
+@pytest.mark.parametrize("smin,smax", [(-3, 3), (-20, 21), (-127, 127)])
+def test_cdf_alphabets_both_forms(smin, smax):
+    """Other alphabet sizes: 7 symbols (the last of the 4 entry slices is empty), 42 (uneven
+    slices), 255 (the largest table, 256 entries): one-lane and four-lane forms give the same
+    tables, and they match the oracle."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    cfg = get_config("gray64", sym_min=smin, sym_max=smax)
+    model, _ = model_for(cfg)
+    rng = np.random.default_rng(53)
+    n = 300_000
+    logits = rng.normal(0, 3, (n, 3))
+    w = np.exp(logits - logits.max(1, keepdims=True))
+    w /= w.sum(1, keepdims=True)
+    mu = rng.uniform(smin - 5, smax + 5, (n, 3))
+    sg = np.exp(rng.uniform(np.log(0.11), np.log(2.0 * (smax - smin)), (n, 3)))
+    prm = torch.from_numpy(np.concatenate([w, mu, sg], 1).astype(np.float32)).cuda()
+    say("cdf alphabet", smin, smax)
+    big = codec.cdf_tables(model, prm).cpu().numpy().view(np.uint16)
+    assert big.shape == (n, smax - smin + 2)
+    check_cdf_rows(big[:1000], prm[:1000].cpu().numpy(), cfg)
+    for m in (1, 65, 5000):
+        part = codec.cdf_tables(model, prm[:m]).cpu().numpy().view(np.uint16)
+        assert np.array_equal(part, big[:m]), m
+
+
 def test_cdf_trim_matches_oracle_definition():
     need_gpu()
     import ctypes
