@@ -512,3 +512,22 @@ def test_lifting_tile_forms_bitwise():
     x6, _ = codec.synthesize(model, ws6, q=q6)
     x3, _ = codec.synthesize(model, ws3, q=q3)
     assert torch.equal(x6[:3], x3)
+
+
+def test_lifting_tile_forms_bitwise_ragged():
+    """Ragged 16 x 32 tiles: twelve 528 x 784 planes (level-1 arrays of 264 x 392, neither a
+    multiple of the tile) take the big tile, three planes the 8 x 16 one; same bits."""
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("lifting tile forms, ragged")
+    cfg = get_config("ycbcr512x768")
+    model, _ = model_for(cfg)
+    x = np.concatenate([sinusoid_1f_planes(528, 784, planes=3, seed=s) for s in (11, 12, 13, 14)])
+    ws12 = codec.Workspace(model, 12, 528, 784)
+    ws3 = codec.Workspace(model, 3, 528, 784)
+    q12, y12, _ = codec.analyze(model, torch.from_numpy(x).cuda(), ws12, want_y=True)
+    q3, y3, _ = codec.analyze(model, torch.from_numpy(x[:3]).cuda(), ws3, want_y=True)
+    assert torch.equal(q12[:3], q3) and torch.equal(y12[:3], y3)
+    x12, _ = codec.synthesize(model, ws12, q=q12)
+    x3, _ = codec.synthesize(model, ws3, q=q3)
+    assert torch.equal(x12[:3], x3)
