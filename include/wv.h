@@ -43,7 +43,8 @@ enum {
     WV_OK = 0,
     WV_EINVAL = -1,       /* bad argument (null pointer, bad enum, bad config) */
     WV_ESHAPE = -2,       /* image or buffer shape not supported */
-    WV_EORDER = -3,       /* subband/step out of range */
+    WV_EORDER = -3,       /* subband/step out of range, or not the successor of the
+                             last call on the same state buffer (coding order) */
     WV_EDEVICE = -4,      /* HIP runtime error or device fault */
     WV_ECORRUPT = -5,     /* corrupt or truncated bitstream */
     WV_EUNSUPPORTED = -6, /* configuration the kernels do not implement */
@@ -184,6 +185,15 @@ int wv_analyze(const wv_model* m, const uint8_t* d_x8, const float* d_xf, int np
 int wv_context_params(const wv_model* m, const int16_t* d_q, int nplanes, int H, int W,
                       int subband, int step, float* d_state, void* d_scratch,
                       float* d_params, void* stream);
+/* Coding order (Sec. 3.2: each step reads the symbols of the steps before it, and
+ * step 0 carries the long context over from the previous subband).  The library
+ * remembers, per state buffer d_state, the (subband, step) of the last call that
+ * returned WV_OK and returns WV_EORDER, launching nothing, for a call that is not
+ * its successor: (i, g + 1) after (i, g) for g < 3, (i + 1, 0) after (i, 3).  (0, 0)
+ * is accepted at any time and starts a new decode; after the last step of the
+ * last subband only (0, 0) is.  With ll_ar = 1 the LL steps 1-3 are optional:
+ * (1, 0) may follow any step of subband 0.  A call that fails leaves the cursor
+ * where it was.  Calls on one state buffer must not overlap in time. */
 
 /*
  * 16-bit CDF tables of n discretised K-component mixtures.  The paper
@@ -260,8 +270,11 @@ int wv_plan_create(const wv_model* m, int ngroups, const wv_group* groups, const
                    void* d_desc, size_t desc_bytes, float* d_params, void* stream, wv_plan** out);
 void wv_plan_destroy(wv_plan* p);
 int wv_plan_rows(const wv_plan* p, int subband, int step, long long* rows, long long* group_first);
-int wv_plan_context_params(const wv_plan* p, int subband, int step, void* stream);
+int wv_plan_context_params(wv_plan* p, int subband, int step, void* stream);
 int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int subband, int step, void* stream);
+
+/* wv_plan_context_params follows the coding order of wv_context_params, with one
+ * cursor for all of the plan's groups (held by the plan). */
 
 /*
  * Continuous batching: one call runs the coding step (subband, step) of each
@@ -274,6 +287,9 @@ int wv_plan_scatter(const wv_plan* p, const uint8_t* d_sym, int subband, int ste
  * untouched until the stream has passed this call) and copied to d_desc
  * asynchronously; *used_bytes receives the bytes needed (n = 0 or
  * h_staging == NULL with d_desc == NULL queries them).  Needs ctx_arch 0.
+ * Every item's (subband, step) must be the successor of the last call on its
+ * d_state (the coding order of wv_context_params); if one is not, the call
+ * returns WV_EORDER and launches nothing.  Two items may not share a d_state.
  */
 typedef struct wv_step_item {
     int H, W, nplanes;
@@ -378,6 +394,30 @@ int wv_rans_encode(const uint16_t* cdf, int nsym, const uint8_t* sym, long long 
                    uint8_t* out, size_t cap, size_t* len);
 int wv_rans_decode(const uint16_t* cdf, int nsym, long long n, const uint8_t* in, size_t len,
                    uint8_t* sym_out);
+
+/*
+ * Graphs of library calls.  wv_graph_begin starts capturing the work that
+ * library calls enqueue on `stream` (a stream created by the caller, not the
+ * default stream; capture mode thread-local); wv_graph_end stops and
+ * instantiates it.  Between the two the caller issues device entry points only
+ * (no host synchronisation, no allocation, no host coder): for example one
+ * coder-elided decode of a plan, every (subband, step)'s
+ * wv_plan_context_params, wv_cdf_tables and wv_plan_scatter, then
+ * wv_synthesize per group.  Host-side checks (shapes, coding order) run once,
+ * at capture; wv_graph_launch replays the recorded kernels with the same
+ * pointers, so every buffer must stay allocated while the graph lives.  Replays
+ * on one stream run in order.  A failed call inside a capture leaves the
+ * capture open: the caller still calls wv_graph_end (which then fails).
+ *
+ * wv_zero: zero `bytes` bytes at the 16-byte aligned device pointer d with a
+ * kernel (replays correctly inside a graph, where memset nodes are avoided).
+ */
+typedef struct wv_graph wv_graph;
+int wv_graph_begin(void* stream);
+int wv_graph_end(void* stream, wv_graph** out);
+int wv_graph_launch(const wv_graph* g, void* stream);
+void wv_graph_destroy(wv_graph* g);
+int wv_zero(void* d, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

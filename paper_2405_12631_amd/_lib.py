@@ -96,6 +96,11 @@ _SIGS = {
     "wv_cdf_untrim": (_I, [_P, _P, _LL, _I, _LL, _P]),
     "wv_rans_encode_trim": (_I, [_P, _P, _LL, _I, _P, _LL, _P, _SZ, ctypes.POINTER(_SZ)]),
     "wv_rans_decode_trim": (_I, [_P, _P, _LL, _I, _LL, _P, _SZ, _P]),
+    "wv_zero": (_I, [_P, _SZ, _P]),
+    "wv_graph_begin": (_I, [_P]),
+    "wv_graph_end": (_I, [_P, ctypes.POINTER(_P)]),
+    "wv_graph_launch": (_I, [_P, _P]),
+    "wv_graph_destroy": (None, [_P]),
 }
 
 _lib = None

@@ -3,8 +3,8 @@
 Images are grouped by size; each group's planes share one set of device
 buffers.  Every layer of a coding step then runs as one persistent launch
 over all groups, the CDF tables of a step as one launch over all groups'
-rows.  The whole decode can be captured in a HIP graph (torch.cuda.CUDAGraph
-over the library's launches) and replayed; `autotune` picks the per-level
+rows.  The whole decode can be captured in a HIP graph of the library's
+launches (wv_graph_*) and replayed; `autotune` picks the per-level
 output-channel blocking by timing replays (the choice never changes bits).
 """
 import ctypes
@@ -127,7 +127,7 @@ class Batch:
         """Coder-elided decode of the whole batch: every step's context model, CDF
         tables and symbol scatter, then synthesis; asynchronous on the current stream."""
         for q in self.q:
-            q.zero_()
+            codec.zero(q)
         for i in range(self.nsub):
             for g in range(4):
                 prm = self.context_params(i, g)
@@ -136,12 +136,10 @@ class Batch:
         return self.synthesize()
 
     def capture(self, syms):
-        """Capture decode_elided in a HIP graph (after one eager warm-up run)."""
+        """Capture decode_elided in a library graph (after one eager warm-up run)."""
         self.decode_elided(syms)
         torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            self.decode_elided(syms)
+        graph = codec.Graph(lambda: self.decode_elided(syms))
         torch.cuda.synchronize()
         return graph
 

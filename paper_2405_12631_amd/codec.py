@@ -38,6 +38,48 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def zero(t):
+    """Zero a device tensor with the library's fill kernel (safe inside a captured graph)."""
+    L.call("wv_zero", _ptr(t), t.numel() * t.element_size(), _stream())
+    return t
+
+
+class Graph:
+    """Library calls captured once (wv_graph_begin / wv_graph_end) and replayed.
+
+    `fn` is run once on a side stream while the library records the work its
+    calls enqueue; it must only call device entry points on preallocated buffers.
+    replay() relaunches the recorded kernels on the current stream."""
+
+    def __init__(self, fn):
+        self.h = None
+        cur = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            s = _stream()
+            L.call("wv_graph_begin", s)
+            h = ctypes.c_void_p()
+            try:
+                fn()
+            finally:
+                rc = L.lib().wv_graph_end(s, _byref(h))
+            L.check(rc)
+        cur.wait_stream(side)
+        self.h = h
+
+    def replay(self):
+        L.call("wv_graph_launch", self.h, _stream())
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            try:
+                L.lib().wv_graph_destroy(h)
+            except Exception:
+                pass
+
+
 class Model:
     """A model handle: weights uploaded and repacked on the current device."""
 
@@ -88,26 +130,40 @@ class Model:
 
 
 class Workspace:
-    """Device state and scratch for nplanes planes of H x W."""
+    """Device state and scratch for nplanes planes of H x W.  With coder=False the
+    buffers of the host-coder path (symbol staging and the trimmed table copies) are
+    left out, as in the coder-elided server."""
 
-    def __init__(self, model, N, H, W):
+    def __init__(self, model, N, H, W, coder=True):
+        self.N, self.H, self.W = N, H, W
+        self.lay = model.layout(H, W)
+        sizes = Workspace.sizes(model, N, H, W, coder)
+        dev = model.device
+        self.state = torch.empty(sizes["state"] // 4, dtype=torch.float32, device=dev)
+        self.scratch = torch.empty(sizes["scratch"] // 4, dtype=torch.float32, device=dev)
+        self.params = torch.empty(sizes["params"] // 4, dtype=torch.float32, device=dev)
+        self.cdf = torch.empty(sizes["cdf"] // 2, dtype=torch.int16, device=dev)
+        if coder:
+            self.sym = torch.empty(sizes["sym"], dtype=torch.uint8, device=dev)
+            # trimmed copy of the CDF rows for the host coder (wv_cdf_trim)
+            self.lolen = torch.empty(sizes["lolen"], dtype=torch.uint8, device=dev)
+            self.packed = torch.empty(sizes["packed"] // 2, dtype=torch.int16, device=dev)
+            self.trim_scratch = torch.empty(sizes["trim_scratch"], dtype=torch.uint8, device=dev)
+
+    @staticmethod
+    def sizes(model, N, H, W, coder=True):
+        """Bytes of every device buffer a Workspace allocates (name -> bytes)."""
         sb, xb = ctypes.c_size_t(), ctypes.c_size_t()
         L.call("wv_workspace_bytes", model.h, N, H, W, _byref(sb), _byref(xb))
-        self.N, self.H, self.W = N, H, W
-        self.state = torch.empty(sb.value // 4, dtype=torch.float32, device=model.device)
-        self.scratch = torch.empty(xb.value // 4, dtype=torch.float32, device=model.device)
-        self.lay = model.layout(H, W)
-        maxg = max(Model.group_count(s["h"], s["w"], 0) for s in self.lay)
-        K = model.cfg["mix_k"]
-        self.params = torch.empty(N * maxg * 3 * K, dtype=torch.float32, device=model.device)
-        self.cdf = torch.empty(N * maxg * (model.nsym + 1), dtype=torch.int16, device=model.device)
-        self.sym = torch.empty(N * maxg, dtype=torch.uint8, device=model.device)
-        # trimmed copy of the CDF rows for the host coder (wv_cdf_trim)
-        tb = ctypes.c_size_t()
-        L.call("wv_cdf_trim_scratch_bytes", N * maxg, _byref(tb))
-        self.lolen = torch.empty(2 * N * maxg, dtype=torch.uint8, device=model.device)
-        self.packed = torch.empty(N * maxg * (model.nsym - 1), dtype=torch.int16, device=model.device)
-        self.trim_scratch = torch.empty(max(tb.value, 8), dtype=torch.uint8, device=model.device)
+        maxg = max(Model.group_count(s["h"], s["w"], 0) for s in model.layout(H, W))
+        out = dict(state=sb.value // 4 * 4, scratch=xb.value // 4 * 4,
+                   params=4 * N * maxg * 3 * model.cfg["mix_k"], cdf=2 * N * maxg * (model.nsym + 1))
+        if coder:
+            tb = ctypes.c_size_t()
+            L.call("wv_cdf_trim_scratch_bytes", N * maxg, _byref(tb))
+            out.update(sym=N * maxg, lolen=2 * N * maxg, packed=2 * N * maxg * (model.nsym - 1),
+                       trim_scratch=max(tb.value, 8))
+        return out
 
 
 # ---------------------------------------------------------------------------

@@ -7,7 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "wv_internal.h"
@@ -981,8 +983,61 @@ extern "C" int wv_impulse_responses(const wv_model* m, const int16_t* d_q, int H
 }
 
 // ---------------------------------------------------------------------------
+// coding order
+// ---------------------------------------------------------------------------
+// Sec. 3.2: step g of a subband reads the symbols its earlier steps decoded, and
+// step 0 advances the ConvLSTM from the previous subband's state, so the calls
+// on one state buffer must follow the coding order.  The library keeps, per
+// state buffer, the position (subband * 4 + step) of the last call that
+// succeeded; a decode that reaches its last step leaves the table.
+namespace {
+struct OrderTable {
+    std::mutex mu;
+    std::unordered_map<const void*, int> last;
+};
+OrderTable& order_table() {
+    static OrderTable* t = new OrderTable();   // never destroyed: calls may come during exit
+    return *t;
+}
+
+// Is (i, g) allowed after `last` (-1: no call yet)?  (0, 0) starts a new decode at
+// any time.  With the autoregressive LL model subband 0 needs only its step 0 (the
+// long context), so (1, 0) may follow any step of subband 0.
+bool order_ok(int last, int i, int g, bool ll_ar) {
+    if (i == 0 && g == 0) return true;
+    if (last < 0) return false;
+    const int li = last >> 2, lg = last & 3;
+    if (ll_ar && li == 0 && i == 1 && g == 0) return true;
+    return lg < 3 ? (i == li && g == lg + 1) : (i == li + 1 && g == 0);
+}
+
+int order_check(const void* key, int i, int g, bool ll_ar, const char* what) {
+    OrderTable& t = order_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    auto it = t.last.find(key);
+    const int last = it == t.last.end() ? -1 : it->second;
+    if (order_ok(last, i, g, ll_ar)) return WV_OK;
+    if (last < 0)
+        return fail(WV_EORDER, "%s: (subband %d, step %d) before (0, 0) on this state buffer", what, i, g);
+    return fail(WV_EORDER, "%s: (subband %d, step %d) does not follow (subband %d, step %d)", what, i, g,
+                last >> 2, last & 3);
+}
+
+void order_commit(const void* key, int i, int g, int nsub) {
+    OrderTable& t = order_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (i == nsub - 1 && g == 3) t.last.erase(key);
+    else t.last[key] = i * 4 + g;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // context model
 // ---------------------------------------------------------------------------
+static int context_params_impl(const wv_model* m, const int16_t* d_q, int N, int H, int W, int i, int g,
+                               float* d_state, void* d_scratch, float* d_params, void* stream,
+                               const std::vector<Sub>& lay);
+
 extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, int H, int W, int i,
                                  int g, float* d_state, void* d_scratch, float* d_params,
                                  void* stream) {
@@ -994,6 +1049,15 @@ extern "C" int wv_context_params(const wv_model* m, const int16_t* d_q, int N, i
     if (rc) return rc;
     if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3)
         return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    if ((rc = order_check(d_state, i, g, m->cfg.ll_ar != 0, "wv_context_params"))) return rc;
+    rc = context_params_impl(m, d_q, N, H, W, i, g, d_state, d_scratch, d_params, stream, lay);
+    if (rc == WV_OK) order_commit(d_state, i, g, (int)lay.size());
+    return rc;
+}
+
+static int context_params_impl(const wv_model* m, const int16_t* d_q, int N, int H, int W, int i, int g,
+                               float* d_state, void* d_scratch, float* d_params, void* stream,
+                               const std::vector<Sub>& lay) {
     const long long ng = wv_group_count(lay[i].h, lay[i].w, g);
     if (ng > 0 && !d_params) return fail(WV_EINVAL, "null pointer");
     if (ng == 0) return WV_OK;   // a 1-wide subband has no positions at this step
@@ -1263,6 +1327,7 @@ struct wv_plan {
     std::vector<std::vector<long long>> row_off;  // [subband * 4 + step] -> per group first row, + total
     char* d_desc;
     float* d_params;
+    int last = -1;   // coding-order cursor of the plan's groups (subband * 4 + step)
 };
 
 static int plan_build(const wv_model* m, int ng, const wv_group* groups, const int* nb_table,
@@ -1469,10 +1534,23 @@ extern "C" int wv_plan_rows(const wv_plan* p, int i, int g, long long* rows, lon
     return WV_OK;
 }
 
-extern "C" int wv_plan_context_params(const wv_plan* p, int i, int g, void* stream) {
+static int plan_step_launch(const wv_plan* p, int i, int g, void* stream);
+
+extern "C" int wv_plan_context_params(wv_plan* p, int i, int g, void* stream) {
     if (!p) return fail(WV_EINVAL, "null plan");
     const int nsub = (int)p->lay[0].size();
     if (i < 0 || i >= nsub || g < 0 || g > 3) return fail(WV_EORDER, "subband %d / step %d out of range", i, g);
+    if (!order_ok(p->last, i, g, p->m->cfg.ll_ar != 0)) {
+        if (p->last < 0) return fail(WV_EORDER, "wv_plan_context_params: (subband %d, step %d) before (0, 0)", i, g);
+        return fail(WV_EORDER, "wv_plan_context_params: (subband %d, step %d) does not follow (subband %d, step %d)",
+                    i, g, p->last >> 2, p->last & 3);
+    }
+    const int rc = plan_step_launch(p, i, g, stream);
+    if (rc == WV_OK) p->last = (i == nsub - 1 && g == 3) ? -1 : i * 4 + g;
+    return rc;
+}
+
+static int plan_step_launch(const wv_plan* p, int i, int g, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const bool bf16 = p->m->precision != WV_FP32;   // BF16 or FP8 kernels
     for (const PlanLaunch& pl : p->steps[i * 4 + g]) {
@@ -1568,6 +1646,7 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     launches[2].mode = CONV_RELU;
     for (int l = 1; l < Lc - 1; ++l) launches[2 + l].mode = CONV_RELU;
     launches.back().mode = CONV_HEAD;
+    std::vector<int> nsubs;   // per item, for the coding-order cursor
     for (int k = 0; k < n; ++k) {
         const wv_step_item& it = items[k];
         if (!it.d_q || !it.d_state || !it.d_scratch || it.nplanes < 1)
@@ -1578,6 +1657,10 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
         const int i = it.subband, g = it.step;
         if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3)
             return fail(WV_EORDER, "item %d: subband %d / step %d out of range", k, i, g);
+        for (int k2 = 0; k2 < k; ++k2)
+            if (items[k2].d_state == it.d_state) return fail(WV_EINVAL, "items %d and %d share a state buffer", k2, k);
+        if ((rc = order_check(it.d_state, i, g, m->cfg.ll_ar != 0, "wv_context_params_items"))) return rc;
+        nsubs.push_back((int)lay.size());
         const Sub& S = lay[i];
         const long long ng = wv_group_count(S.h, S.w, g);
         if (ng > 0 && !it.d_params) return fail(WV_EINVAL, "item %d: null params", k);
@@ -1660,7 +1743,10 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
         total += (Lx.segs.size() + 255) & ~(size_t)255;
     }
     if (used_bytes) *used_bytes = total;
-    if (total == 0) return WV_OK;
+    if (total == 0) {   // only empty steps: nothing to launch, the items still advance
+        for (int k = 0; k < n; ++k) order_commit(items[k].d_state, items[k].subband, items[k].step, nsubs[k]);
+        return WV_OK;
+    }
     if (!h_staging || !d_desc) return fail(WV_EINVAL, "null staging or descriptor buffer");
     if (total > staging_bytes || total > desc_bytes)
         return fail(WV_ENOMEM, "descriptors need %zu bytes", total);
@@ -1684,5 +1770,61 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
             HIPCHK(launch_conv_seg(reinterpret_cast<const ConvSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
                                    Lx.proto, Lx.mode, Lx.nb, grid, s));
     }
+    for (int k = 0; k < n; ++k) order_commit(items[k].d_state, items[k].subband, items[k].step, nsubs[k]);
     return WV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// graphs of library calls, and a zero fill that can be captured
+// ---------------------------------------------------------------------------
+struct wv_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" int wv_zero(void* d, size_t bytes, void* stream) {
+    if (!bytes) return WV_OK;
+    if (!d) return fail(WV_EINVAL, "null pointer");
+    if ((uintptr_t)d & 15) return fail(WV_EINVAL, "wv_zero needs a 16-byte aligned pointer");
+    HIPCHK(launch_zero(d, bytes, (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" int wv_graph_begin(void* stream) {
+    if (!stream) return fail(WV_EINVAL, "capture needs a stream other than the default stream");
+    HIPCHK(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    return WV_OK;
+}
+
+extern "C" int wv_graph_end(void* stream, wv_graph** out) {
+    if (!stream || !out) return fail(WV_EINVAL, "null pointer");
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(WV_EDEVICE, "capture failed: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(WV_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    *out = new wv_graph{g, x};
+    return WV_OK;
+}
+
+extern "C" int wv_graph_launch(const wv_graph* g, void* stream) {
+    if (!g) return fail(WV_EINVAL, "null graph");
+    HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return WV_OK;
+}
+
+extern "C" void wv_graph_destroy(wv_graph* g) {
+    if (!g) return;
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+

@@ -137,6 +137,27 @@ struct ConvSeg16 {
     long long item0;
 };
 
+// One segment of a fused step-stack launch (wv_stack_bf16.hip): a plane group's
+// subband at one coding step.  Layers 0..2 (64 -> 64 BF16, ReLU; layer 0 with the
+// symbol chunk wsym when step >= 1) and the head (64 -> 3K, one column block),
+// packed as MfmaLayer16.  Work items: planes x vertical segments of seg_rows rows x
+// strips of 58 columns.
+struct StackSeg {
+    const uint16_t* w16[4];
+    const uint16_t* wsym;
+    const float* bias[4];
+    const uint16_t* in16;   // l_i, NHWC BF16 [N][h][w][64]
+    long long in_ps;        // plane stride (elements)
+    const int16_t* sym;     // this subband's symbols of plane 0 in the packed layout, or null
+    long long sym_ps;
+    float* params;          // [N][n_g][3K]
+    int N, h, w, step, K;
+    float sigma_min;
+    int strips_x, segs_y, seg_rows;
+    long long item0;
+};
+constexpr int STACK_STRIP = 58;   // output columns per strip
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s);
@@ -146,6 +167,9 @@ hipError_t launch_conv_seg(const ConvSeg* segs, int nseg, long long total, const
                            int mode, int nb, int grid, hipStream_t s);
 hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total,
                                 const MfmaLayer16& proto, int mode, int nb, int grid, hipStream_t s);
+// Fused BF16 step stacks over device segment arrays (has_sym: every segment has step >= 1).
+hipError_t launch_stack_bf16(const StackSeg* segs, int nseg, long long total, int has_sym, int grid,
+                             hipStream_t s);
 // Output blocks per workgroup chosen for a launch of `tiles` position tiles.
 int conv_pick_nb(int nbt, int mode, long long tiles, int lowp);
 int conv_tile_h(int bf16);
@@ -186,6 +210,8 @@ hipError_t launch_ar_decode(const ArModel& M, const ArStreams& S, int16_t* q, lo
 hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A,
                              View out, int N, int h, int w, int predict, float sign, int lift_int,
                              hipStream_t s);
+// Zero `bytes` bytes at p (16-byte aligned) with a kernel.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_center_u8(const uint8_t* x8, float* xf, long long n, hipStream_t s);
 hipError_t launch_quantize(const float* y, int16_t* q, int N, long long per_plane, long long n_ll,
                            float dL, float dH, int smin, int smax, int* clip, hipStream_t s);

@@ -261,6 +261,17 @@ __global__ __launch_bounds__(BLK) void sir_pyramid_k(const unsigned long long* _
     }
 }
 
+// Zero fill with 16-byte stores and a byte tail (a kernel, so that it can sit in a
+// captured graph where a memset node would not be replayed reliably).
+__global__ __launch_bounds__(BLK) void zero_k(uint8_t* __restrict__ p, size_t bytes) {
+    const size_t n16 = bytes >> 4;
+    const size_t stride = (size_t)gridDim.x * BLK;
+    for (size_t e = (size_t)blockIdx.x * BLK + threadIdx.x; e < n16; e += stride)
+        reinterpret_cast<uint4*>(p)[e] = make_uint4(0, 0, 0, 0);
+    const size_t t = (n16 << 4) + (size_t)blockIdx.x * BLK + threadIdx.x;
+    if (t < bytes && t < (n16 << 4) + 16) p[t] = 0;
+}
+
 __global__ void fill_u64_k(unsigned long long* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -318,6 +329,14 @@ hipError_t launch_dwconv(const float* in, const float* w, const float* b, float*
     if (n == 0) return hipSuccess;
     if (C % 4) return hipErrorInvalidValue;
     hipLaunchKernelGGL(dwconv_k, dim3(nblocks(n)), dim3(BLK), 0, s, in, w, b, out, N, h, w_, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (!bytes) return hipSuccess;
+    const size_t n16 = (bytes >> 4) + 1;
+    const unsigned grid = (unsigned)std::min<size_t>((n16 + BLK - 1) / BLK, 4096);
+    hipLaunchKernelGGL(zero_k, dim3(grid), dim3(BLK), 0, s, (uint8_t*)p, bytes);
     return hipGetLastError();
 }
 

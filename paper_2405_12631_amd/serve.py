@@ -59,15 +59,12 @@ class Prepared:
 
 
 def footprint(model, prep):
-    """Device bytes a request holds while active."""
+    """Device bytes a request holds while active: every buffer of its slot's
+    workspaces (coder-elided form), its symbols (int16) and its reconstruction (float)."""
     total = 0
     for H, W, N, _, _ in prep.groups:
-        sb, xb = ctypes.c_size_t(), ctypes.c_size_t()
-        L.call("wv_workspace_bytes", model.h, N, H, W, _byref(sb), _byref(xb))
-        lay = model.layout(H, W)
-        maxg = max(codec.Model.group_count(s["h"], s["w"], 0) for s in lay)
-        total += sb.value + xb.value + N * H * W * (2 + 4) + N * maxg * (3 * model.cfg["mix_k"] * 4 +
-                                                                         (model.nsym + 1) * 2)
+        total += sum(codec.Workspace.sizes(model, N, H, W, coder=False).values())
+        total += N * H * W * (2 + 4)
     return total
 
 
@@ -77,7 +74,7 @@ class Slot:
         self.i, self.g = 0, 0
         self.ws, self.q, self.xhat = [], [], []
         for H, W, N, _, _ in prep.groups:
-            ws = codec.Workspace(model, N, H, W)
+            ws = codec.Workspace(model, N, H, W, coder=False)
             self.ws.append(ws)
             self.q.append(torch.zeros((N, H * W), dtype=torch.int16, device=model.device))
             self.xhat.append(torch.empty((N, H, W), dtype=torch.float32, device=model.device))
@@ -126,9 +123,10 @@ class Slot:
 class Server:
     """FIFO admission by footprint, continuous batching, one coding step per iteration."""
 
-    def __init__(self, model, budget_bytes, staging_bytes=16 << 20):
+    def __init__(self, model, budget_bytes, staging_bytes=16 << 20, on_params=None):
         self.model = model
         self.budget = budget_bytes
+        self.on_params = on_params      # optional hook(slot, group, subband, step, params) for checks
         self.staging = [torch.empty(staging_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
         self.desc = [torch.empty(staging_bytes, dtype=torch.uint8, device=model.device) for _ in range(2)]
         self.staging_ev = [None, None]
@@ -147,6 +145,13 @@ class Server:
         ev = torch.cuda.Event()
         ev.record(torch.cuda.current_stream())
         self.staging_ev[k] = ev
+        if self.on_params is not None:
+            for s in slots:
+                for b, ws in enumerate(s.ws):
+                    lay = ws.lay[s.i]
+                    ng = codec.Model.group_count(lay["h"], lay["w"], s.g)
+                    K = self.model.cfg["mix_k"]
+                    self.on_params(s, b, s.i, s.g, ws.params[:ws.N * ng * 3 * K].view(ws.N, ng, 3 * K))
         return [s for s in slots if s.after_params(self.model)]
 
     def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None, keep_outputs=False):
@@ -161,6 +166,7 @@ class Server:
         iters = 0
         rejected = 0
         peak_active = 0
+        mid_joins = 0      # admissions while another request was past its first step
         fp = {pid: footprint(m, p) for pid, p in preps.items()}
         while True:
             now = time.perf_counter() - t0
@@ -174,6 +180,7 @@ class Server:
             while queue and used + fp[queue[0][1]] <= self.budget:
                 t_arr, pid = queue.popleft()
                 slot = Slot(m, dict(arrival=t_arr, prep=pid, admitted=now), preps[pid])
+                mid_joins += any((a.i, a.g) != (0, 0) for a in active)
                 used += fp[pid]
                 active.append(slot)
             peak_active = max(peak_active, len(active))
@@ -203,7 +210,7 @@ class Server:
         lat = np.array([s.req["finished"] - s.req["arrival"] for s in done]) if done else np.zeros(0)
         px = sum(s.prep.pixels for s in done)
         stats = dict(completed=len(done), rejected=rejected, left_queued=len(queue) + len(pending),
-                     left_active=len(active), peak_active=peak_active,
+                     left_active=len(active), peak_active=peak_active, mid_decode_joins=mid_joins,
                      iterations=iters, wall_s=round(wall, 3), mpx_per_s=round(px / wall / 1e6, 3),
                      p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 2) if len(lat) else None,
                      p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 2) if len(lat) else None)

@@ -3,8 +3,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle as O
 from wvgen import get_config, make_weights, pack_weights, sinusoid_1f_planes
-from gpu_common import need_gpu, say
+from gpu_common import PARAM_RTOL, XHAT_ATOL, check_cdf_rows, need_gpu, param_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -115,16 +116,14 @@ def test_single_image_graph_replays_equal_eager(prec):
     xhat = torch.empty((3, 64, 96), dtype=torch.float32, device="cuda")
 
     def step():
-        q.zero_()
+        codec.zero(q)
         codec.decode_elided(model, syms, ws, q, xhat)
 
     step()
     torch.cuda.synchronize()
     ref_q, ref_x = q.clone(), xhat.clone()
     assert torch.equal(ref_q, q_known)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step()
+    graph = codec.Graph(step)          # wv_graph_begin / wv_graph_end around the library calls
     for _ in range(3):
         q.fill_(7)
         xhat.fill_(-1.0)
@@ -166,3 +165,57 @@ def test_wide_and_narrow_channel_blocking_bitwise():
             ref = codec.context_params(model, q, ws, i, g).reshape(-1)
             lo = first[gb] * 3 * K
             assert torch.equal(a[lo:lo + ref.numel()], ref), (i, g)
+
+
+def test_plan_decode_matches_oracle_fp32():
+    """A mixed-size FP32 plan (a 256 x 256 image, two 64 x 96 images, a 48 x 80 image and a
+    1088 x 1920 image, three planes each) decoded through the persistent plan launches: every
+    group's parameters (plane 0) against the FP64 oracle on the same symbols, at every
+    (subband, step) (for 1088 x 1920 the level-4 and level-3 subbands, whose oracle finishes in
+    seconds), one step's CDF rows against the oracle's tables of those parameters, and every
+    group's reconstruction (plane 0; the 1088 x 1920 planes take the 16 x 32 lifting tile)."""
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B
+    say("plan vs oracle fp32")
+    cfg = get_config("ycbcr512x768")
+    w = make_weights(cfg)
+    model = codec.Model(cfg, pack_weights(cfg, w))
+    sizes = [(256, 256), (64, 96), (48, 80), (1088, 1920), (64, 96)]
+    bt = B.Batch(model, sizes)
+    bt.load_images(_images(sizes, seed=51))
+    syms = bt.known_symbols()
+    K = cfg["mix_k"]
+    qs = {b: O.unpack(bt.q[b][:1].cpu().numpy().astype(np.int64), cfg, ws.H, ws.W) for b, ws in enumerate(bt.ws)}
+    checked = {b: (13 if ws.H * ws.W <= 256 * 256 else 7) for b, ws in enumerate(bt.ws)}
+    got = {b: [] for b in qs}
+    for q in bt.q:
+        codec.zero(q)
+    for i in range(bt.nsub):
+        for g in range(4):
+            prm = bt.context_params(i, g)
+            n, first = bt.rows(i, g)
+            for b, ws in enumerate(bt.ws):
+                if i < checked[b]:
+                    lay = ws.lay[i]
+                    ng = codec.Model.group_count(lay["h"], lay["w"], g)
+                    lo = first[b] * 3 * K
+                    got[b].append(prm[lo:lo + ng * 3 * K].cpu().numpy().reshape(ng, 3 * K))
+            cdf = bt.cdf_tables(prm)
+            if (i, g) == (12, 2):
+                check_cdf_rows(cdf[:n].cpu().numpy().view(np.uint16), prm[:n * 3 * K].cpu().numpy(), cfg)
+            bt.scatter(syms[i][g], i, g)
+    xh = bt.synthesize()
+    torch.cuda.synchronize()
+    for b, ws in enumerate(bt.ws):
+        ls = O.long_context(qs[b], cfg, w, upto=checked[b])
+        worst = 0.0
+        for i in range(checked[b]):
+            for g in range(4):
+                ref = O.step_params(qs[b][i], ls[i], ws.lay[i]["type"], g, cfg, w)[0]
+                worst = max(worst, param_err(got[b][4 * i + g], ref, K))
+        say(f"group {ws.H}x{ws.W}: worst param rel err {worst:.2e} over {checked[b]} subbands")
+        assert worst <= PARAM_RTOL, (ws.H, ws.W, worst)
+        ref_x = O.synthesize(O.dequantize(qs[b], cfg), cfg, w)[0]
+        err = float(np.max(np.abs(xh[b][0].cpu().numpy() - ref_x)))
+        say(f"group {ws.H}x{ws.W}: xhat err {err:.2e}")
+        assert err <= XHAT_ATOL, (ws.H, ws.W, err)

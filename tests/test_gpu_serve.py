@@ -46,10 +46,19 @@ def test_served_results_equal_alone_results(prec):
     # Staggered arrivals: later requests join while earlier ones are mid-decode.
     reqs = [(0.0, 0), (0.0, 2), (0.004, 1), (0.008, 0), (0.012, 2), (0.02, 1)]
     budget = 3 * max(serve.footprint(model, p) for p in preps.values())     # forces queueing
-    srv = serve.Server(model, budget)
+    seen = {}
+
+    def record(slot, b, i, g, prm):   # parameters of the first request of input 1, as served
+        if slot.prep is preps[1] and seen.setdefault("slot", slot) is slot:
+            seen[(b, i, g)] = prm.cpu().numpy().copy()
+
+    srv = serve.Server(model, budget, on_params=record if prec == "fp32" else None)
     stats, done = srv.run(reqs, preps, max_seconds=60, keep_outputs=True)
     say(stats)
     assert stats["completed"] == len(reqs) and stats["rejected"] == 0
+    # Continuous batching happened: requests were active together, and some joined while
+    # another was past its first step.
+    assert stats["peak_active"] > 1 and stats["mid_decode_joins"] >= 1, stats
     alone = {pid: _alone(model, p) for pid, p in preps.items()}
     for s in done:
         for b, x in enumerate(s.xhat):
@@ -58,3 +67,18 @@ def test_served_results_equal_alone_results(prec):
     g = [s for s in done if s.req["prep"] == 2][0]
     err = (g.xhat[0].cpu().numpy() - luma.astype(np.float32)).std()
     assert err < 8.0, err
+    if prec == "fp32":
+        # The served FP32 request against the FP64 oracle on the same symbols: every plane's
+        # parameters at every (subband, step), and the reconstruction.
+        import oracle as O
+        from gpu_common import PARAM_RTOL, XHAT_ATOL, param_err
+        w = make_weights(cfg)
+        H, W, N, q_known, _ = preps[1].groups[0]
+        qs = O.unpack(q_known.cpu().numpy().astype(np.int64), cfg, H, W)
+        ref = O.context_params_all(qs, cfg, w)
+        worst = max(param_err(seen[(0, i, g)], ref[i][g], cfg["mix_k"]) for i in range(len(ref)) for g in range(4))
+        say("served request vs oracle: worst param rel err", worst)
+        assert worst <= PARAM_RTOL
+        s1 = [s for s in done if s.req["prep"] == 1][0]
+        ref_x = O.synthesize(O.dequantize(qs, cfg), cfg, w)
+        assert np.max(np.abs(s1.xhat[0].cpu().numpy() - ref_x)) <= XHAT_ATOL
