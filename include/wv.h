@@ -373,6 +373,20 @@ int wv_temporal_haar_inverse(float* d_frames, int T, long long n, void* stream);
 int wv_cdf_trim_scratch_bytes(long long n, size_t* bytes);
 int wv_cdf_trim(const uint16_t* d_cdf, long long n, int nsym, uint8_t* d_lolen, uint16_t* d_packed,
                 long long packed_cap, void* d_scratch, size_t scratch_bytes, void* stream);
+/*
+ * wv_cdf_trim_noalloc: wv_cdf_trim for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and stream order as wv_cdf_trim, without
+ * the scratch argument: the block sums go to a 256 KiB array of the library's
+ * own (a file-scope device array, one per GPU, held until the process ends), so
+ * at most 8,388,608 rows per call (more: WV_ENOMEM, nothing launched).  The call
+ * allocates nothing.  Every call on a GPU uses that GPU's one array and leaves
+ * its contents behind (each entry a call reads it first writes, so nothing needs
+ * clearing); calls that overlap in time on one GPU (two streams, two threads)
+ * race on it and must be serialised by the caller.
+ */
+int wv_cdf_trim_noalloc(const uint16_t* d_cdf, long long n, int nsym, uint8_t* d_lolen, uint16_t* d_packed,
+                        long long packed_cap, void* stream);
 int wv_cdf_untrim(const uint8_t* lolen, const uint16_t* packed, long long packed_count, int nsym,
                   long long n, uint16_t* cdf_out);
 int wv_rans_encode_trim(const uint8_t* lolen, const uint16_t* packed, long long packed_count, int nsym,

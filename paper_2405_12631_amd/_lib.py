@@ -93,6 +93,7 @@ _SIGS = {
     "wv_rans_decode": (_I, [_P, _I, _LL, _P, _SZ, _P]),
     "wv_cdf_trim_scratch_bytes": (_I, [_LL, ctypes.POINTER(_SZ)]),
     "wv_cdf_trim": (_I, [_P, _LL, _I, _P, _P, _LL, _P, _SZ, _P]),
+    "wv_cdf_trim_noalloc": (_I, [_P, _LL, _I, _P, _P, _LL, _P]),
     "wv_cdf_untrim": (_I, [_P, _P, _LL, _I, _LL, _P]),
     "wv_rans_encode_trim": (_I, [_P, _P, _LL, _I, _P, _LL, _P, _SZ, ctypes.POINTER(_SZ)]),
     "wv_rans_decode_trim": (_I, [_P, _P, _LL, _I, _LL, _P, _SZ, _P]),

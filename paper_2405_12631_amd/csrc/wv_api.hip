@@ -1256,6 +1256,22 @@ extern "C" int wv_cdf_trim(const uint16_t* d_cdf, long long n, int nsym, uint8_t
     return WV_OK;
 }
 
+extern "C" int wv_cdf_trim_noalloc(const uint16_t* d_cdf, long long n, int nsym, uint8_t* d_lolen,
+                                   uint16_t* d_packed, long long packed_cap, void* stream) {
+    if (n < 0) return fail(WV_ESHAPE, "negative row count");
+    if (nsym < 2 || nsym > 255) return fail(WV_EUNSUPPORTED, "alphabet must have 2..255 symbols");
+    if (n == 0) return WV_OK;
+    if (!d_cdf || !d_lolen || !d_packed) return fail(WV_EINVAL, "null pointer");
+    if (n > TRIM_STATIC_MAX_ROWS)
+        return fail(WV_ENOMEM, "wv_cdf_trim_noalloc handles at most %lld rows (got %lld); use wv_cdf_trim",
+                    TRIM_STATIC_MAX_ROWS, n);
+    if (packed_cap < n * (long long)(nsym - 1)) return fail(WV_ENOMEM, "packed buffer below n (nsym - 1)");
+    long long* scratch = nullptr;
+    HIPCHK(cdf_trim_static_scratch(&scratch));
+    HIPCHK(launch_cdf_trim(d_cdf, n, nsym, d_lolen, d_packed, scratch, (hipStream_t)stream));
+    return WV_OK;
+}
+
 static int sym_io(const wv_config* cfg, int N, int H, int W, int i, int g, std::vector<Sub>& lay) {
     int rc = check_cfg(cfg);
     if (rc) return rc;

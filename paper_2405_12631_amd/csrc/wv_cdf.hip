@@ -20,6 +20,8 @@
 #include "wv_device.h"
 #include "wv_internal.h"
 
+#include <mutex>
+
 namespace wv {
 namespace {
 
@@ -203,6 +205,32 @@ __global__ __launch_bounds__(256) void trim_write_k(const uint16_t* __restrict__
 }  // namespace
 
 size_t cdf_trim_scratch_bytes(long long n) { return (size_t)((n + 255) / 256) * sizeof(long long); }
+
+// Block sums of the trim for callers that cannot allocate: one array per GPU, held
+// until the process ends.  Host code never passes `trim_scratch` itself (in host code
+// the name is not a device address); it passes the address hipGetSymbolAddress gives
+// for the current device, looked up once per device.
+namespace {
+__device__ __align__(256) long long trim_scratch[TRIM_STATIC_SCRATCH_BYTES / sizeof(long long)];
+std::mutex g_trim_mu;
+long long* g_trim_ptr[TRIM_MAX_DEVICES];
+}  // namespace
+
+hipError_t cdf_trim_static_scratch(long long** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= TRIM_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_trim_mu);
+    if (!g_trim_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(trim_scratch));
+        if (e != hipSuccess) return e;
+        g_trim_ptr[dev] = static_cast<long long*>(p);
+    }
+    *out = g_trim_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_cdf_trim(const uint16_t* cdf, long long n, int nsym, uint8_t* lolen, uint16_t* packed,
                            long long* scratch, hipStream_t s) {

@@ -236,6 +236,12 @@ hipError_t launch_scatter(const uint8_t* sym, int16_t* q, int N, long long q_ps,
 hipError_t launch_gather(const int16_t* q, uint8_t* sym, int N, long long q_ps, long long off,
                          int h, int w, int step, int smin, hipStream_t s);
 size_t cdf_trim_scratch_bytes(long long n);
+// The trim's scratch as a file-scope device array (wv_cdf_trim_noalloc): its size, and
+// its address on the current device (looked up once per device).
+constexpr size_t TRIM_STATIC_SCRATCH_BYTES = 256 * 1024;
+constexpr long long TRIM_STATIC_MAX_ROWS = (long long)(TRIM_STATIC_SCRATCH_BYTES / sizeof(long long)) * 256;
+constexpr int TRIM_MAX_DEVICES = 64;
+hipError_t cdf_trim_static_scratch(long long** out);
 hipError_t launch_cdf_trim(const uint16_t* cdf, long long n, int nsym, uint8_t* lolen, uint16_t* packed,
                            long long* scratch, hipStream_t s);
 hipError_t launch_cdf(const float* params, long long n, int K, int dist, int smin, int nsym,
