@@ -1332,7 +1332,27 @@ struct PlanLaunch {
     long long total;     // work items
     MfmaLayer proto;
     MfmaLayer16 proto16;
+    int fused = 0;       // 1: a whole step stack in one launch (StackSeg array)
+    int has_sym = 0;
 };
+
+// Whether a model's step stacks can run as one fused launch per step (wv_stack_bf16.hip):
+// BF16, 64 channels, three ReLU layers and the head, the head's 3K outputs in one
+// 16-column block.  WV_FUSED_STACKS=0 keeps the layer-by-layer launches (tests compare
+// the two forms).
+bool stack_fusable(const wv_model* m) {
+    const char* env = getenv("WV_FUSED_STACKS");
+    if (env && env[0] == '0') return false;
+    return m->precision == WV_BF16 && m->cfg.ctx_arch == 0 && m->cfg.ctx_ch == 64 && m->cfg.ctx_layers == 4 &&
+           3 * m->cfg.mix_k <= 16;
+}
+
+// Rows per work item of a fused launch: whole strips up to 128 rows, else even pieces of
+// at most 128 rows (each piece recomputes 3 rows of context above and below).
+int stack_seg_rows(int h) {
+    const int pieces = (h + 127) / 128;
+    return (h + pieces - 1) / pieces;
+}
 }  // namespace
 
 struct wv_plan {
@@ -1380,8 +1400,9 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
             const int type = P->lay[0][i].type;
             const int level = P->lay[0][i].level;
             const int nlayers = (int)(bf16 ? m->ctx16[type][g].size() : m->ctx[type][g].size());
-            // launch list: LSTM at step 0, then the stack's layers
-            for (int l = (g == 0 ? -1 : 0); l < nlayers; ++l) {
+            const bool fuse = stack_fusable(m);
+            // launch list: LSTM at step 0, then the stack's layers (or the fused stack)
+            for (int l = (g == 0 ? -1 : 0); l < (fuse ? 0 : nlayers); ++l) {
                 const bool lstm = l < 0;
                 const bool last = l == nlayers - 1;
                 const int mode = lstm ? CONV_LSTM : (last ? CONV_HEAD : CONV_RELU);
@@ -1488,6 +1509,58 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 P->steps[i * 4 + g].push_back(pl);
                 host.resize((host.size() + 255) & ~(size_t)255);
             }
+            if (fuse) {
+                const std::vector<MfmaLayer16>& Ls = m->ctx16[type][g];
+                PlanLaunch pl{};
+                host.resize((host.size() + 255) & ~(size_t)255);
+                pl.seg_off = host.size();
+                pl.nseg = ng;
+                pl.fused = 1;
+                pl.has_sym = g > 0;
+                long long item = 0;
+                for (int b = 0; b < ng; ++b) {
+                    const wv_group& G = groups[b];
+                    const Sub& S = P->lay[b][i];
+                    const size_t SS = state_floats(m->cfg, G.nplanes, G.H, G.W);
+                    float* hcur = G.d_state + (size_t)(i & 1) * 2 * SS;
+                    StackSeg sg{};
+                    for (int l = 0; l < 4; ++l) {
+                        sg.w16[l] = Ls[l].w;
+                        sg.bias[l] = Ls[l].bias;
+                    }
+                    sg.wsym = g > 0 ? Ls[0].wsym : nullptr;
+                    sg.in16 = reinterpret_cast<const uint16_t*>(hcur);
+                    sg.in_ps = (long long)S.h * S.w * C;
+                    sg.sym = g > 0 ? G.d_q + S.off : nullptr;
+                    sg.sym_ps = (long long)G.H * G.W;
+                    sg.params = P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr;
+                    sg.N = G.nplanes;
+                    sg.h = S.h;
+                    sg.w = S.w;
+                    sg.step = g;
+                    sg.K = m->cfg.mix_k;
+                    sg.sigma_min = m->cfg.sigma_min;
+                    sg.strips_x = (S.w + STACK_STRIP - 1) / STACK_STRIP;
+                    sg.seg_rows = stack_seg_rows(S.h);
+                    sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
+                    sg.item0 = item;
+                    const size_t at = host.size();
+                    host.resize(at + sizeof(StackSeg));
+                    memcpy(host.data() + at, &sg, sizeof sg);
+                    // a step with no positions (1-wide subband) still needs no items
+                    if (wv_group_count(S.h, S.w, g) > 0)
+                        item += (long long)sg.strips_x * sg.segs_y * G.nplanes;
+                    else {
+                        StackSeg* back = reinterpret_cast<StackSeg*>(host.data() + at);
+                        back->strips_x = back->segs_y = 1;
+                        back->N = 0;
+                    }
+                }
+                pl.total = item;
+                pl.grid = (int)(item < 256 ? item : 256);
+                P->steps[i * 4 + g].push_back(pl);
+                host.resize((host.size() + 255) & ~(size_t)255);
+            }
         }
     }
     return WV_OK;
@@ -1570,6 +1643,11 @@ static int plan_step_launch(const wv_plan* p, int i, int g, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const bool bf16 = p->m->precision != WV_FP32;   // BF16 or FP8 kernels
     for (const PlanLaunch& pl : p->steps[i * 4 + g]) {
+        if (pl.fused) {
+            HIPCHK(launch_stack_bf16(reinterpret_cast<const StackSeg*>(p->d_desc + pl.seg_off), pl.nseg, pl.total,
+                                     pl.has_sym, pl.grid, s));
+            continue;
+        }
         if (bf16)
             HIPCHK(launch_conv_seg_bf16(reinterpret_cast<const ConvSeg16*>(p->d_desc + pl.seg_off), pl.nseg,
                                         pl.total, pl.proto16, pl.mode, pl.nb, pl.grid, s));

@@ -219,3 +219,32 @@ def test_plan_decode_matches_oracle_fp32():
         err = float(np.max(np.abs(xh[b][0].cpu().numpy() - ref_x)))
         say(f"group {ws.H}x{ws.W}: xhat err {err:.2e}")
         assert err <= XHAT_ATOL, (ws.H, ws.W, err)
+
+
+def test_fused_step_stacks_equal_layer_by_layer_bitwise():
+    """The fused BF16 step-stack kernel (one launch per step: three ReLU layers and the head
+    with activations in LDS) against the layer-by-layer launches, bit for bit, on every
+    (subband, step) of a plan with tall subbands split into row pieces (1088 x 1920: level 1 is
+    544 rows in five pieces, 17 strips with a ragged last one), a 256 x 256 image and a small
+    ragged one."""
+    import os
+    need_gpu()
+    from paper_2405_12631_amd import codec, batch as B, WV_BF16
+    say("fused stacks vs layer by layer")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    sizes = [(1088, 1920), (256, 256), (48, 80)]
+    imgs = _images(sizes, seed=61)
+    os.environ["WV_FUSED_STACKS"] = "0"
+    try:
+        layered = B.Batch(model, sizes)
+    finally:
+        del os.environ["WV_FUSED_STACKS"]
+    fused = B.Batch(model, sizes)
+    layered.load_images(imgs)
+    fused.load_images(imgs)
+    for i in range(fused.nsub):
+        for g in range(4):
+            a = fused.context_params(i, g)
+            b = layered.context_params(i, g)
+            assert torch.equal(a, b), (i, g)
