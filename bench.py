@@ -256,8 +256,11 @@ def bench_serve(args):
     of 8 frames 1088x1920 4:2:0 (temporal Haar, then the spatial codec per temporal
     subband), BF16 context convs, admission by HBM footprint, continuous batching.
     Each request refers to one of a few prepared inputs (symbols on the device, the
-    coder elided).  Runs the offered rate and a lower rate; value = sustained Mpixel/s
-    (luma pixels x frames for GOPs) under the offered rate."""
+    coder elided).  Runs the offered rate over the arrival window, a bisection for the
+    highest rate whose p99 stays stable, that rate over the full window, and the same
+    arrivals through the host coder (tables trimmed and copied to the host, rANS on host
+    threads); value = sustained Mpixel/s (luma pixels x frames for GOPs) under the offered
+    rate."""
     import torch
     from paper_2405_12631_amd import codec, serve
     from wvgen import get_config, make_weights, pack_weights, poisson_arrivals, sinusoid_1f_planes, \
@@ -272,7 +275,8 @@ def bench_serve(args):
         ids = []
         for r in range(2):
             pid = len(preps)
-            preps[pid] = serve.Prepared(model, "image", sinusoid_1f_planes(hw[0], hw[1], 3, seed=100 + 2 * k + r))
+            preps[pid] = serve.Prepared(model, "image", sinusoid_1f_planes(hw[0], hw[1], 3, seed=100 + 2 * k + r),
+                                        coder=args.serve_coder_seconds > 0)
             ids.append(pid)
         by_size[tuple(hw)] = ids
     gops = []
@@ -280,19 +284,19 @@ def bench_serve(args):
         luma, chroma = video_gop_420(T=cfg["gop"], H=cfg["video_hw"][0], W=cfg["video_hw"][1],
                                      seed=5 + r, shift_px=cfg["shift_px"])
         pid = len(preps)
-        preps[pid] = serve.Prepared(model, "gop", (luma, chroma))
+        preps[pid] = serve.Prepared(model, "gop", (luma, chroma), coder=args.serve_coder_seconds > 0)
         gops.append(pid)
     torch.cuda.synchronize()
     budget = int(args.serve_budget_gb * (1 << 30))
 
-    def run(rate, seconds):
+    def run(rate, seconds, coder=False):
         arr = poisson_arrivals(rate, seconds, cfg["frac_video"], cfg["sizes"], seed=cfg["seed_arrivals"])
         reqs = []
         for n, a in enumerate(arr):
             pid = gops[n % 2] if a["kind"] == "gop" else by_size[a["size"]][n % 2]
             reqs.append((a["t"], pid))
         offered = sum(preps[p].pixels for _, p in reqs) / seconds / 1e6
-        srv = serve.Server(model, budget)
+        srv = serve.Server(model, budget, coder=coder)
         stats, done = srv.run(reqs, preps, admit_until=seconds, max_seconds=seconds + args.serve_drain, log=log)
         # p99 stability: requests arriving in the second half of the window against those of
         # the first half; stable if every arrival finished and the later p99 is at most 1.5x the
@@ -334,6 +338,11 @@ def bench_serve(args):
         best = run(lo_r, args.serve_seconds)
         runs["search"] = search
         runs[f"best_{lo_r:g}_req_s"] = best
+    if args.serve_coder_seconds > 0:
+        # The same arrivals through the host coder: tables trimmed on the device and copied to
+        # the host every iteration, rANS decoding on host threads, symbols copied back.
+        crate = (best or hi)["rate_hz"]
+        runs[f"coder_{crate:g}_req_s"] = run(crate, args.serve_coder_seconds, coder=True)
     out = dict(
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
         value=hi["mpx_per_s"], unit="Mpixel/s", n_gpus=1, steps=hi["iterations"], warmup=0,
@@ -347,6 +356,7 @@ def bench_serve(args):
                     budget_gib=args.serve_budget_gb),
         p50_ms=hi["p50_ms"], p99_ms=hi["p99_ms"],
         highest_stable_rate_hz=(best or {}).get("rate_hz"),
+        coder_run={k: v for k, v in runs.items() if k.startswith("coder_")},
         highest_stable=best, runs=runs,
     )
     print(json.dumps(out))
@@ -639,6 +649,8 @@ def main():
                          "offered rate, then a search for the highest rate with a stable p99")
     ap.add_argument("--serve-search-seconds", type=float, default=15.0,
                     help="arrival window of each step of the stable-rate search")
+    ap.add_argument("--serve-coder-seconds", type=float, default=20.0,
+                    help="arrival window of the host-coder run at the highest stable rate (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=150.0, help="HBM admission budget")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -134,15 +134,16 @@ class Workspace:
     buffers of the host-coder path (symbol staging and the trimmed table copies) are
     left out, as in the coder-elided server."""
 
-    def __init__(self, model, N, H, W, coder=True):
+    def __init__(self, model, N, H, W, coder=True, step_buffers=True):
         self.N, self.H, self.W = N, H, W
         self.lay = model.layout(H, W)
-        sizes = Workspace.sizes(model, N, H, W, coder)
+        sizes = Workspace.sizes(model, N, H, W, coder, step_buffers)
         dev = model.device
         self.state = torch.empty(sizes["state"] // 4, dtype=torch.float32, device=dev)
         self.scratch = torch.empty(sizes["scratch"] // 4, dtype=torch.float32, device=dev)
-        self.params = torch.empty(sizes["params"] // 4, dtype=torch.float32, device=dev)
-        self.cdf = torch.empty(sizes["cdf"] // 2, dtype=torch.int16, device=dev)
+        if step_buffers:
+            self.params = torch.empty(sizes["params"] // 4, dtype=torch.float32, device=dev)
+            self.cdf = torch.empty(sizes["cdf"] // 2, dtype=torch.int16, device=dev)
         if coder:
             self.sym = torch.empty(sizes["sym"], dtype=torch.uint8, device=dev)
             # trimmed copy of the CDF rows for the host coder (wv_cdf_trim)
@@ -151,13 +152,19 @@ class Workspace:
             self.trim_scratch = torch.empty(sizes["trim_scratch"], dtype=torch.uint8, device=dev)
 
     @staticmethod
-    def sizes(model, N, H, W, coder=True):
+    def max_step_rows(model, N, H, W):
+        """Rows (coefficients) of the largest coding step of N planes of H x W."""
+        return N * max(Model.group_count(s["h"], s["w"], 0) for s in model.layout(H, W))
+
+    @staticmethod
+    def sizes(model, N, H, W, coder=True, step_buffers=True):
         """Bytes of every device buffer a Workspace allocates (name -> bytes)."""
         sb, xb = ctypes.c_size_t(), ctypes.c_size_t()
         L.call("wv_workspace_bytes", model.h, N, H, W, _byref(sb), _byref(xb))
-        maxg = max(Model.group_count(s["h"], s["w"], 0) for s in model.layout(H, W))
-        out = dict(state=sb.value // 4 * 4, scratch=xb.value // 4 * 4,
-                   params=4 * N * maxg * 3 * model.cfg["mix_k"], cdf=2 * N * maxg * (model.nsym + 1))
+        maxg = Workspace.max_step_rows(model, 1, H, W)
+        out = dict(state=sb.value // 4 * 4, scratch=xb.value // 4 * 4)
+        if step_buffers:
+            out.update(params=4 * N * maxg * 3 * model.cfg["mix_k"], cdf=2 * N * maxg * (model.nsym + 1))
         if coder:
             tb = ctypes.c_size_t()
             L.call("wv_cdf_trim_scratch_bytes", N * maxg, _byref(tb))

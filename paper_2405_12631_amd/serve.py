@@ -3,21 +3,29 @@
 Requests arrive over time (Poisson), wait in a FIFO queue and are admitted as
 soon as their HBM footprint fits the budget.  Every admitted request owns
 device-resident buffers for its plane groups (symbols, ConvLSTM state,
-scratch, parameters, CDF tables, reconstruction).  Each iteration advances
-every active request by one coding step: one wv_context_params_items call
-runs all of their layers as a handful of persistent launches whatever their
-positions and sizes, then each request's CDF tables and symbol scatter run,
-and requests that finished their last step are synthesised (GOPs: inverse
-temporal Haar afterwards) and retired.  New requests join at step (0, 0)
-while others are mid-decode.
+scratch, reconstruction).  Each iteration advances every active request by one
+coding step: one wv_context_params_items call runs all of their layers as a
+handful of persistent launches whatever their positions and sizes, writing the
+parameters of all requests into one shared buffer, so that one wv_cdf_tables
+launch builds every row's table; then the step's symbols are scattered, and
+requests that finished their last step are synthesised (GOPs: inverse
+temporal Haar afterwards) and retired.  New requests join at step (0, 0) while
+others are mid-decode.
 
-The entropy coder is elided: each request refers to a prepared input whose
-per-step symbols are already on the device (they stand in for the host
-coder's output), so the server measures the GPU decode path under load.
+Symbols come from one of two places:
+* coder elided (default): each request refers to a prepared input whose
+  per-step symbols are already on the device (they stand in for the host
+  coder's output), so the server measures the GPU decode path under load;
+* host coder (coder=True): the iteration's tables are trimmed on the device
+  (wv_cdf_trim), copied to the host in two transfers, the rANS streams of every
+  request are decoded by a thread pool, and the symbols go back in one
+  transfer.  The run then reports the PCIe bytes moved and the coder threads'
+  busy time.
 """
 import ctypes
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -29,16 +37,17 @@ _byref = ctypes.byref
 
 
 class Prepared:
-    """An encoded input: plane groups with their per-step symbols on the device."""
+    """An encoded input: plane groups with their per-step symbols on the device and, with
+    coder=True, the rANS streams of each plane (streams[n][subband][step])."""
 
-    def __init__(self, model, kind, data, gop_levels=3):
+    def __init__(self, model, kind, data, gop_levels=3, coder=False):
         self.kind = kind
-        self.groups = []          # (H, W, nplanes, q_known, syms[i][g])
+        self.groups = []          # (H, W, nplanes, q_known, syms[i][g], streams | None)
         if kind == "image":
             x = torch.from_numpy(np.ascontiguousarray(data)).to(model.device)
             N, H, W = x.shape
             self.pixels = H * W
-            self._add(model, x, H, W, N)
+            self._add(model, x, H, W, N, coder)
         else:
             luma, chroma = data            # [T][H][W], [T][2][H/2][W/2] uint8
             T, H, W = luma.shape
@@ -48,23 +57,40 @@ class Prepared:
                 f = codec.center_u8(torch.from_numpy(np.ascontiguousarray(planes)).to(model.device))
                 codec.temporal_haar(f)                      # temporal subbands, first axis
                 f = f.reshape(-1, f.shape[-2], f.shape[-1]).contiguous()
-                self._add(model, f, f.shape[1], f.shape[2], f.shape[0])
+                self._add(model, f, f.shape[1], f.shape[2], f.shape[0], coder)
         torch.cuda.synchronize()
 
-    def _add(self, model, x, H, W, N):
+    def _add(self, model, x, H, W, N, coder):
         ws = codec.Workspace(model, N, H, W)
         q, _, _ = codec.analyze(model, x, ws)
         syms = codec.prepare_elided(model, q, ws)
-        self.groups.append((H, W, N, q, syms))
+        streams = None
+        if coder:
+            data, q_enc = codec.encode(model, x, ws=codec.Workspace(model, N, H, W))
+            assert torch.equal(q_enc, q)
+            streams = codec.unpack_stream(model, data)[3]
+        self.groups.append((H, W, N, q, syms, streams))
 
 
-def footprint(model, prep):
-    """Device bytes a request holds while active: every buffer of its slot's
-    workspaces (coder-elided form), its symbols (int16) and its reconstruction (float)."""
+def _shared_row_bytes(model, coder):
+    """Device bytes per row of the server's shared step buffers: 3K float parameters and
+    one CDF row (int16 [nsym + 1]); with the host coder also the trimmed copy ((lo, len)
+    and at most nsym - 1 values), a symbol byte and the trim's block sums."""
+    b = 4 * 3 * model.cfg["mix_k"] + 2 * (model.nsym + 1)
+    if coder:
+        b += 2 + 2 * (model.nsym - 1) + 1 + 1
+    return b
+
+
+def footprint(model, prep, coder=False):
+    """Device bytes a request holds while active: its workspaces (state and scratch), its
+    symbols (int16) and reconstruction (float), and its share of the server's step buffers
+    (the rows of its largest coding step)."""
     total = 0
-    for H, W, N, _, _ in prep.groups:
-        total += sum(codec.Workspace.sizes(model, N, H, W, coder=False).values())
+    for H, W, N, _, _, _ in prep.groups:
+        total += sum(codec.Workspace.sizes(model, N, H, W, coder=False, step_buffers=False).values())
         total += N * H * W * (2 + 4)
+        total += codec.Workspace.max_step_rows(model, N, H, W) * _shared_row_bytes(model, coder)
     return total
 
 
@@ -73,28 +99,23 @@ class Slot:
         self.req, self.prep = req, prep
         self.i, self.g = 0, 0
         self.ws, self.q, self.xhat = [], [], []
-        for H, W, N, _, _ in prep.groups:
-            ws = codec.Workspace(model, N, H, W, coder=False)
+        for H, W, N, _, _, _ in prep.groups:
+            ws = codec.Workspace(model, N, H, W, coder=False, step_buffers=False)
             self.ws.append(ws)
             self.q.append(torch.zeros((N, H * W), dtype=torch.int16, device=model.device))
             self.xhat.append(torch.empty((N, H, W), dtype=torch.float32, device=model.device))
         self.nsub = len(self.ws[0].lay)
         self.done_event = None
 
-    def items(self):
+    def rows(self):
+        """Rows of this slot's current step, per group."""
         out = []
-        for b, ws in enumerate(self.ws):
-            out.append(L.wv_step_item(ws.H, ws.W, ws.N, self.q[b].data_ptr(), ws.state.data_ptr(),
-                                      ws.scratch.data_ptr(), self.i, self.g, ws.params.data_ptr()))
+        for ws in self.ws:
+            s = ws.lay[self.i]
+            out.append(ws.N * codec.Model.group_count(s["h"], s["w"], self.g))
         return out
 
-    def after_params(self, model):
-        for b, ws in enumerate(self.ws):
-            s = ws.lay[self.i]
-            ng = codec.Model.group_count(s["h"], s["w"], self.g)
-            prm = ws.params[:ws.N * ng * 3 * model.cfg["mix_k"]]
-            codec.cdf_tables(model, prm, out=ws.cdf)
-            codec.scatter_symbols(model, self.prep.groups[b][4][self.i][self.g], self.q[b], ws, self.i, self.g)
+    def advance(self):
         self.g += 1
         if self.g == 4:
             self.i, self.g = self.i + 1, 0
@@ -123,22 +144,62 @@ class Slot:
 class Server:
     """FIFO admission by footprint, continuous batching, one coding step per iteration."""
 
-    def __init__(self, model, budget_bytes, staging_bytes=16 << 20, on_params=None):
+    def __init__(self, model, budget_bytes, staging_bytes=16 << 20, on_params=None, coder=False,
+                 coder_threads=16):
         self.model = model
         self.budget = budget_bytes
         self.on_params = on_params      # optional hook(slot, group, subband, step, params) for checks
+        self.coder = coder
         self.staging = [torch.empty(staging_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
         self.desc = [torch.empty(staging_bytes, dtype=torch.uint8, device=model.device) for _ in range(2)]
         self.staging_ev = [None, None]
+        self.rows_cap = 0
+        self.pool = ThreadPoolExecutor(max_workers=coder_threads) if coder else None
+        self.coder_threads = coder_threads
+        self.d2h = self.h2d = 0
+        self.coder_busy = 0.0
+
+    def _grow(self, rows):
+        """Shared step buffers for `rows` rows (grown between iterations when needed)."""
+        if rows <= self.rows_cap:
+            return
+        m, dev = self.model, self.model.device
+        cap = max(rows, 2 * self.rows_cap)
+        self.params = torch.empty(cap * 3 * m.cfg["mix_k"], dtype=torch.float32, device=dev)
+        self.cdf = torch.empty(cap * (m.nsym + 1), dtype=torch.int16, device=dev)
+        if self.coder:
+            tb = ctypes.c_size_t()
+            L.call("wv_cdf_trim_scratch_bytes", cap, _byref(tb))
+            self.lolen = torch.empty(2 * cap, dtype=torch.uint8, device=dev)
+            self.packed = torch.empty(cap * (m.nsym - 1), dtype=torch.int16, device=dev)
+            self.trim_scratch = torch.empty(max(tb.value, 8), dtype=torch.uint8, device=dev)
+            self.sym = torch.empty(cap, dtype=torch.uint8, device=dev)
+            self.sym_h = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
+        self.rows_cap = cap
 
     def step(self, slots, k):
         """One iteration over the active slots using staging buffer k."""
-        items = [it for s in slots for it in s.items()]
+        m = self.model
+        K = m.cfg["mix_k"]
+        rows = [s.rows() for s in slots]
+        total = sum(sum(r) for r in rows)
+        self._grow(max(total, 1))
+        items, first = [], []
+        at = 0
+        for s, rs in zip(slots, rows):
+            fs = []
+            for b, ws in enumerate(s.ws):
+                items.append(L.wv_step_item(ws.H, ws.W, ws.N, s.q[b].data_ptr(), ws.state.data_ptr(),
+                                            ws.scratch.data_ptr(), s.i, s.g,
+                                            self.params.data_ptr() + 4 * at * 3 * K))
+                fs.append(at)
+                at += rs[b]
+            first.append(fs)
         arr = (L.wv_step_item * len(items))(*items)
         if self.staging_ev[k] is not None:
             self.staging_ev[k].synchronize()        # staging k is free once its copy ran
         used = ctypes.c_size_t()
-        L.call("wv_context_params_items", self.model.h, len(items), arr,
+        L.call("wv_context_params_items", m.h, len(items), arr,
                ctypes.c_void_p(self.staging[k].data_ptr()), self.staging[k].numel(),
                ctypes.c_void_p(self.desc[k].data_ptr()), self.desc[k].numel(), _byref(used),
                codec._stream())
@@ -146,17 +207,62 @@ class Server:
         ev.record(torch.cuda.current_stream())
         self.staging_ev[k] = ev
         if self.on_params is not None:
-            for s in slots:
+            for s, fs, rs in zip(slots, first, rows):
                 for b, ws in enumerate(s.ws):
-                    lay = ws.lay[s.i]
-                    ng = codec.Model.group_count(lay["h"], lay["w"], s.g)
-                    K = self.model.cfg["mix_k"]
-                    self.on_params(s, b, s.i, s.g, ws.params[:ws.N * ng * 3 * K].view(ws.N, ng, 3 * K))
-        return [s for s in slots if s.after_params(self.model)]
+                    prm = self.params[fs[b] * 3 * K:(fs[b] + rs[b]) * 3 * K]
+                    self.on_params(s, b, s.i, s.g, prm.view(ws.N, rs[b] // ws.N, 3 * K))
+        if total:
+            codec.cdf_tables(m, self.params[:total * 3 * K], out=self.cdf)
+        if self.coder and total:
+            self._decode_symbols(slots, first, rows, total)
+        for s, fs, rs in zip(slots, first, rows):
+            for b, ws in enumerate(s.ws):
+                if not rs[b]:
+                    continue
+                sym = self.sym[fs[b]:fs[b] + rs[b]] if self.coder else s.prep.groups[b][4][s.i][s.g]
+                codec.scatter_symbols(m, sym, s.q[b], ws, s.i, s.g)
+        return [s for s in slots if s.advance()]
 
-    def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None, keep_outputs=False):
+    def _decode_symbols(self, slots, first, rows, total):
+        """Host coder for one iteration: trim every row on the device, copy the trimmed
+        tables to the host, decode each request's streams on the thread pool, copy the
+        symbols back."""
+        m = self.model
+        cdf = self.cdf[:total * (m.nsym + 1)].view(total, m.nsym + 1)
+        L.call("wv_cdf_trim", codec._ptr(cdf), total, m.nsym, codec._ptr(self.lolen), codec._ptr(self.packed),
+               self.packed.numel(), codec._ptr(self.trim_scratch), self.trim_scratch.numel(), codec._stream())
+        lolen = self.lolen[:2 * total].cpu().numpy()
+        npk = int(lolen[1::2].astype(np.int64).sum())
+        packed = self.packed[:npk].cpu().numpy().view(np.uint16)
+        self.d2h += lolen.nbytes + packed.nbytes
+        tr = codec.Trimmed(lolen, packed, m.nsym)
+        out = self.sym_h.numpy()
+
+        def work(a, b, data):
+            t0 = time.perf_counter()
+            out[a:b] = codec.rans_decode_trim(tr, a, b, data)
+            return time.perf_counter() - t0
+
+        futs = []
+        for s, fs, rs in zip(slots, first, rows):
+            for b, ws in enumerate(s.ws):
+                if not rs[b]:
+                    continue
+                streams = s.prep.groups[b][5]
+                per = rs[b] // ws.N
+                for n in range(ws.N):
+                    a = fs[b] + n * per
+                    futs.append(self.pool.submit(work, a, a + per, streams[n][s.i][s.g]))
+        self.coder_busy += sum(f.result() for f in futs)
+        self.sym[:total].copy_(self.sym_h[:total], non_blocking=True)
+        self.h2d += total
+
+    def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None, keep_outputs=False,
+            tick=None):
         """requests: list of (arrival_s, prep_id) sorted by time.  Returns (stats, slots);
-        finished slots keep their reconstruction only if keep_outputs."""
+        finished slots keep their reconstruction only if keep_outputs.  With tick set, time
+        is virtual: it advances by `tick` per iteration (and jumps to the next arrival when
+        nothing is active), so admissions do not depend on the host's speed (tests)."""
         m = self.model
         pending = deque(requests)
         queue, active, finishing, done = deque(), [], [], []
@@ -167,9 +273,12 @@ class Server:
         rejected = 0
         peak_active = 0
         mid_joins = 0      # admissions while another request was past its first step
-        fp = {pid: footprint(m, p) for pid, p in preps.items()}
+        self.d2h = self.h2d = 0
+        self.coder_busy = 0.0
+        fp = {pid: footprint(m, p, self.coder) for pid, p in preps.items()}
+        vclock = 0.0
         while True:
-            now = time.perf_counter() - t0
+            now = vclock if tick is not None else time.perf_counter() - t0
             while pending and pending[0][0] <= now and (admit_until is None or pending[0][0] <= admit_until):
                 queue.append(pending.popleft())
             if admit_until is not None and now > admit_until:
@@ -193,8 +302,10 @@ class Server:
                     active.remove(s)
                     finishing.append(s)
             for s in list(finishing):
+                if tick is not None:
+                    s.done_event.synchronize()
                 if s.done_event.query():
-                    s.req["finished"] = time.perf_counter() - t0
+                    s.req["finished"] = vclock if tick is not None else time.perf_counter() - t0
                     finishing.remove(s)
                     used -= fp[s.req["prep"]]
                     s.release(keep_outputs)
@@ -203,7 +314,11 @@ class Server:
                 break
             if now > max_seconds:
                 break
-            if not active and not finishing and queue == deque() and pending:
+            if tick is not None:   # monotone: one tick per loop, or a jump to the next arrival
+                vclock += tick
+                if not active and not finishing and pending:
+                    vclock = max(vclock, pending[0][0])
+            elif not active and not finishing and queue == deque() and pending:
                 time.sleep(max(0.0, min(pending[0][0] - now, 0.01)))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -214,6 +329,12 @@ class Server:
                      iterations=iters, wall_s=round(wall, 3), mpx_per_s=round(px / wall / 1e6, 3),
                      p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 2) if len(lat) else None,
                      p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 2) if len(lat) else None)
+        if self.coder:
+            stats.update(coder_threads=self.coder_threads,
+                         coder_utilisation=round(self.coder_busy / (self.coder_threads * wall), 4),
+                         pcie_d2h_gb_per_s=round(self.d2h / wall / 1e9, 3),
+                         pcie_h2d_gb_per_s=round(self.h2d / wall / 1e9, 4),
+                         table_bytes_to_host=self.d2h)
         if log:
             log(f"served {stats}")
         return stats, done

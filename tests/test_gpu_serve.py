@@ -13,7 +13,7 @@ def _alone(model, prep):
     """Decode one prepared input by itself with the single-request calls."""
     from paper_2405_12631_amd import codec
     outs = []
-    for H, W, N, q_known, syms in prep.groups:
+    for H, W, N, q_known, syms, _ in prep.groups:
         ws = codec.Workspace(model, N, H, W)
         q = torch.zeros_like(q_known)
         for i in range(len(ws.lay)):
@@ -43,8 +43,9 @@ def test_served_results_equal_alone_results(prec):
     preps = {0: serve.Prepared(model, "image", sinusoid_1f_planes(64, 96, 3, seed=1)),
              1: serve.Prepared(model, "image", sinusoid_1f_planes(32, 48, 3, seed=2)),
              2: serve.Prepared(model, "gop", (luma, chroma))}
-    # Staggered arrivals: later requests join while earlier ones are mid-decode.
-    reqs = [(0.0, 0), (0.0, 2), (0.004, 1), (0.008, 0), (0.012, 2), (0.02, 1)]
+    # Staggered arrivals on the server's virtual clock (one unit per iteration; a request
+    # takes 52 iterations): later requests join while earlier ones are mid-decode.
+    reqs = [(0.0, 0), (0.0, 2), (4.0, 1), (8.0, 0), (12.0, 2), (20.0, 1)]
     budget = 3 * max(serve.footprint(model, p) for p in preps.values())     # forces queueing
     seen = {}
 
@@ -53,7 +54,7 @@ def test_served_results_equal_alone_results(prec):
             seen[(b, i, g)] = prm.cpu().numpy().copy()
 
     srv = serve.Server(model, budget, on_params=record if prec == "fp32" else None)
-    stats, done = srv.run(reqs, preps, max_seconds=60, keep_outputs=True)
+    stats, done = srv.run(reqs, preps, max_seconds=1e9, keep_outputs=True, tick=1.0)
     say(stats)
     assert stats["completed"] == len(reqs) and stats["rejected"] == 0
     # Continuous batching happened: requests were active together, and some joined while
@@ -73,7 +74,7 @@ def test_served_results_equal_alone_results(prec):
         import oracle as O
         from gpu_common import PARAM_RTOL, XHAT_ATOL, param_err
         w = make_weights(cfg)
-        H, W, N, q_known, _ = preps[1].groups[0]
+        H, W, N, q_known, _, _ = preps[1].groups[0]
         qs = O.unpack(q_known.cpu().numpy().astype(np.int64), cfg, H, W)
         ref = O.context_params_all(qs, cfg, w)
         worst = max(param_err(seen[(0, i, g)], ref[i][g], cfg["mix_k"]) for i in range(len(ref)) for g in range(4))
@@ -82,3 +83,29 @@ def test_served_results_equal_alone_results(prec):
         s1 = [s for s in done if s.req["prep"] == 1][0]
         ref_x = O.synthesize(O.dequantize(qs, cfg), cfg, w)
         assert np.max(np.abs(s1.xhat[0].cpu().numpy() - ref_x)) <= XHAT_ATOL
+
+
+def test_served_with_host_coder_equals_alone():
+    """The coder-inclusive server: every iteration's tables trimmed on the device, copied to
+    the host, decoded by the host rANS threads from real GPU-encoded streams, symbols copied
+    back.  The decoded symbols and reconstructions equal the coder-elided lone decodes bit
+    for bit (FP32 and BF16 context)."""
+    need_gpu()
+    from paper_2405_12631_amd import codec, serve, WV_BF16
+    say("serve with host coder")
+    cfg = get_config("ycbcr512x768")
+    model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
+    luma, chroma = video_gop_420(T=8, H=64, W=64, seed=7)
+    preps = {0: serve.Prepared(model, "image", sinusoid_1f_planes(64, 96, 3, seed=3), coder=True),
+             1: serve.Prepared(model, "gop", (luma, chroma), coder=True),
+             2: serve.Prepared(model, "image", sinusoid_1f_planes(32, 48, 3, seed=4), coder=True)}
+    reqs = [(0.0, 0), (0.0, 1), (3.0, 2), (6.0, 0), (10.0, 1)]
+    srv = serve.Server(model, 8 * max(serve.footprint(model, p, coder=True) for p in preps.values()), coder=True)
+    stats, done = srv.run(reqs, preps, max_seconds=1e9, keep_outputs=True, tick=1.0)
+    say(stats)
+    assert stats["completed"] == len(reqs) and stats["mid_decode_joins"] >= 1
+    assert stats["table_bytes_to_host"] > 0 and 0 < stats["coder_utilisation"] <= 1.0
+    alone = {pid: _alone(model, p) for pid, p in preps.items()}
+    for s in done:
+        for b, x in enumerate(s.xhat):
+            assert torch.equal(x, alone[s.req["prep"]][b]), (s.req, b)
