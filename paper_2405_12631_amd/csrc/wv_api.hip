@@ -1353,6 +1353,40 @@ int stack_seg_rows(int h) {
     const int pieces = (h + 127) / 128;
     return (h + pieces - 1) / pieces;
 }
+
+// Fused step-stack segment of a plane group's subband S at step g: input l_i = hcur
+// (BF16 NHWC), symbols of this subband (plane 0) at q_sub with plane stride q_ps.
+// Returns the segment's work items (0 for a step with no positions).
+long long make_stack_seg(const wv_model* m, int type, int g, const float* hcur, const Sub& S, int nplanes,
+                         const int16_t* q_sub, long long q_ps, float* params, long long item0, StackSeg& sg) {
+    const std::vector<MfmaLayer16>& Ls = m->ctx16[type][g];
+    sg = StackSeg{};
+    for (int l = 0; l < 4; ++l) {
+        sg.w16[l] = Ls[l].w;
+        sg.bias[l] = Ls[l].bias;
+    }
+    sg.wsym = g > 0 ? Ls[0].wsym : nullptr;
+    sg.in16 = reinterpret_cast<const uint16_t*>(hcur);
+    sg.in_ps = (long long)S.h * S.w * m->cfg.ctx_ch;
+    sg.sym = g > 0 ? q_sub : nullptr;
+    sg.sym_ps = q_ps;
+    sg.params = params;
+    sg.N = nplanes;
+    sg.h = S.h;
+    sg.w = S.w;
+    sg.step = g;
+    sg.K = m->cfg.mix_k;
+    sg.sigma_min = m->cfg.sigma_min;
+    sg.strips_x = (S.w + STACK_STRIP - 1) / STACK_STRIP;
+    sg.seg_rows = stack_seg_rows(S.h);
+    sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
+    sg.item0 = item0;
+    if (wv_group_count(S.h, S.w, g) == 0) {   // a 1-wide subband's empty step
+        sg.N = 0;
+        return 0;
+    }
+    return (long long)sg.strips_x * sg.segs_y * nplanes;
+}
 }  // namespace
 
 struct wv_plan {
@@ -1510,7 +1544,6 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 host.resize((host.size() + 255) & ~(size_t)255);
             }
             if (fuse) {
-                const std::vector<MfmaLayer16>& Ls = m->ctx16[type][g];
                 PlanLaunch pl{};
                 host.resize((host.size() + 255) & ~(size_t)255);
                 pl.seg_off = host.size();
@@ -1522,39 +1555,13 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                     const wv_group& G = groups[b];
                     const Sub& S = P->lay[b][i];
                     const size_t SS = state_floats(m->cfg, G.nplanes, G.H, G.W);
-                    float* hcur = G.d_state + (size_t)(i & 1) * 2 * SS;
-                    StackSeg sg{};
-                    for (int l = 0; l < 4; ++l) {
-                        sg.w16[l] = Ls[l].w;
-                        sg.bias[l] = Ls[l].bias;
-                    }
-                    sg.wsym = g > 0 ? Ls[0].wsym : nullptr;
-                    sg.in16 = reinterpret_cast<const uint16_t*>(hcur);
-                    sg.in_ps = (long long)S.h * S.w * C;
-                    sg.sym = g > 0 ? G.d_q + S.off : nullptr;
-                    sg.sym_ps = (long long)G.H * G.W;
-                    sg.params = P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr;
-                    sg.N = G.nplanes;
-                    sg.h = S.h;
-                    sg.w = S.w;
-                    sg.step = g;
-                    sg.K = m->cfg.mix_k;
-                    sg.sigma_min = m->cfg.sigma_min;
-                    sg.strips_x = (S.w + STACK_STRIP - 1) / STACK_STRIP;
-                    sg.seg_rows = stack_seg_rows(S.h);
-                    sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
-                    sg.item0 = item;
+                    const float* hcur = G.d_state + (size_t)(i & 1) * 2 * SS;
+                    StackSeg sg;
+                    item += make_stack_seg(m, type, g, hcur, S, G.nplanes, G.d_q + S.off, (long long)G.H * G.W,
+                                           P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr, item, sg);
                     const size_t at = host.size();
                     host.resize(at + sizeof(StackSeg));
                     memcpy(host.data() + at, &sg, sizeof sg);
-                    // a step with no positions (1-wide subband) still needs no items
-                    if (wv_group_count(S.h, S.w, g) > 0)
-                        item += (long long)sg.strips_x * sg.segs_y * G.nplanes;
-                    else {
-                        StackSeg* back = reinterpret_cast<StackSeg*>(host.data() + at);
-                        back->strips_x = back->segs_y = 1;
-                        back->N = 0;
-                    }
                 }
                 pl.total = item;
                 pl.grid = (int)(item < 256 ? item : 256);
@@ -1679,6 +1686,7 @@ namespace {
 struct ItemLaunch {
     std::vector<char> segs;
     int nseg = 0, mode = 0, nb = 1;
+    int fused = 0, has_sym = 0;   // fused step stacks: segs holds StackSeg
     long long total = 0;
     long long tiles = 0;
     MfmaLayer proto{};
@@ -1734,12 +1742,18 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     const int th = conv_tile_h(bf16), tw = conv_tile_w(bf16);
     // Launch roles: 0 LSTM, 1 first layer without symbols (step 0), 2 first layer with
     // symbols, 3 + (l - 1) inner layer l, last: the head.
-    std::vector<ItemLaunch> launches(3 + (Lc - 2) + 1);
+    const bool fuse = stack_fusable(m);
+    // fused step stacks (steps 0 and >= 1) after the per-layer roles
+    std::vector<ItemLaunch> launches(3 + (Lc - 2) + 1 + 2);
+    const int fuse0 = 3 + (Lc - 2) + 1;
+    launches[fuse0].fused = 1;
+    launches[fuse0 + 1].fused = 1;
+    launches[fuse0 + 1].has_sym = 1;
     launches[0].mode = CONV_LSTM;
     launches[1].mode = CONV_RELU;
     launches[2].mode = CONV_RELU;
     for (int l = 1; l < Lc - 1; ++l) launches[2 + l].mode = CONV_RELU;
-    launches.back().mode = CONV_HEAD;
+    launches[fuse0 - 1].mode = CONV_HEAD;
     std::vector<int> nsubs;   // per item, for the coding-order cursor
     for (int k = 0; k < n; ++k) {
         const wv_step_item& it = items[k];
@@ -1800,6 +1814,16 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
             item_seg(launches[0], bf16, bf16 ? nullptr : &m->lstm, bf16 ? &m->lstm16 : nullptr, a);
         }
         if (ng == 0) continue;
+        if (fuse) {
+            ItemLaunch& Fl = launches[fuse0 + (g > 0)];
+            StackSeg sg;
+            Fl.total += make_stack_seg(m, S.type, g, hcur, S, it.nplanes, it.d_q + S.off, HW, it.d_params, Fl.total, sg);
+            const size_t at = Fl.segs.size();
+            Fl.segs.resize(at + sizeof(StackSeg));
+            memcpy(Fl.segs.data() + at, &sg, sizeof sg);
+            Fl.nseg++;
+            continue;
+        }
         for (int l = 0; l < Lc; ++l) {
             const bool last = l == Lc - 1;
             ConvArgs a = base;
@@ -1826,14 +1850,14 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
                 a.out16 = reinterpret_cast<uint16_t*>(a.out);
                 a.out = nullptr;
             }
-            const int role = l == 0 ? (g > 0 ? 2 : 1) : (last ? (int)launches.size() - 1 : 2 + l);
+            const int role = l == 0 ? (g > 0 ? 2 : 1) : (last ? fuse0 - 1 : 2 + l);
             item_seg(launches[role], bf16, bf16 ? nullptr : &m->ctx[S.type][g][l],
                      bf16 ? &m->ctx16[S.type][g][l] : nullptr, a);
         }
     }
     size_t total = 0;
     for (auto& Lx : launches) {
-        item_finish(Lx, bf16);
+        if (!Lx.fused) item_finish(Lx, bf16);
         total += (Lx.segs.size() + 255) & ~(size_t)255;
     }
     if (used_bytes) *used_bytes = total;
@@ -1856,6 +1880,11 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     for (size_t r = 0; r < launches.size(); ++r) {
         const ItemLaunch& Lx = launches[r];
         if (!Lx.nseg || !Lx.total) continue;
+        if (Lx.fused) {
+            HIPCHK(launch_stack_bf16(reinterpret_cast<const StackSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
+                                     Lx.has_sym, (int)(Lx.total < 256 ? Lx.total : 256), s));
+            continue;
+        }
         const int grid = (int)(Lx.total < 1024 ? Lx.total : 1024);
         if (bf16)
             HIPCHK(launch_conv_seg_bf16(reinterpret_cast<const ConvSeg16*>((char*)d_desc + offs[r]), Lx.nseg,
