@@ -53,10 +53,13 @@ constexpr int NCH = 64;            // channels of every layer input
 constexpr int CC = NCH / 32;       // K chunks per tap
 constexpr int NK = 9 * CC;         // K steps per layer
 
-__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (v_cvt_pk_bf16_f32)
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
+}
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {   // two values, one instruction
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){lo, hi}, bf16x2));
 }
 __device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ floatx4 mfma(uint4 a, uint4 b, floatx4 c) {
@@ -118,7 +121,7 @@ __device__ __forceinline__ void row_mfma(const uint8_t* rin, int x, int mb0, con
 #pragma unroll
         for (int mb = 0; mb < MBN; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(a[st & 1][mb], wr[st][nb], acc[mb][nb]);
+            for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(wr[st][nb], a[st & 1][mb], acc[mb][nb]);
         // Keep the next step's fragment reads ahead of this step's MFMAs (two fragment sets
         // live): the latency of an LDS read is then covered by a step of MFMAs.
         if (st + 1 < NK) __builtin_amdgcn_sched_group_barrier(0x100, MBN, 0);
@@ -146,7 +149,7 @@ __device__ __forceinline__ void row_sym(const uint16_t (*rs)[SLOTS], int x, cons
         const uint4 av = make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
                                     e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
 #pragma unroll
-        for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(av, ws[nb], acc[mb][nb]);
+        for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(ws[nb], av, acc[mb][nb]);
         __builtin_amdgcn_sched_barrier(0);   // one block's symbol reads at a time (register budget)
     }
 }
@@ -181,8 +184,10 @@ __device__ __forceinline__ void wave_run(const StackSeg* __restrict__ segs, int 
     uint4 ws[NBX];   // layer 0's symbol-chunk fragments (steps >= 1)
     uint4 wh[NK][1];
     const uint16_t* wcur = nullptr;
-    float bias[NBX];
-    float hbias = 0.f;
+    // Accumulators are transposed (weights are the MFMA's first operand): lane holds
+    // output channels 4 (lane / 16) .. + 3 of block nb for position lane % 16 of block mb.
+    float bias[NBX][4];
+    float hbias[4] = {0.f, 0.f, 0.f, 0.f};
     long long it = blockIdx.x;
     int si;
     Item I;
@@ -197,7 +202,9 @@ __device__ __forceinline__ void wave_run(const StackSeg* __restrict__ segs, int 
 #pragma unroll
                     for (int nb = 0; nb < NBL; ++nb) wr[st][nb] = ld_g(wg + (st * 4 + nb0 + nb) * 64 + lane);
 #pragma unroll
-                for (int nb = 0; nb < NBL; ++nb) bias[nb] = gmem(S.bias[l])[(nb0 + nb) * 16 + col];
+                for (int nb = 0; nb < NBL; ++nb)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) bias[nb][k] = gmem(S.bias[l])[(nb0 + nb) * 16 + rowq + k];
             }
             if (NBL > 0 && SYM && l == 0) {
                 const uint4* wsg = reinterpret_cast<const uint4*>(S.wsym);
@@ -208,7 +215,8 @@ __device__ __forceinline__ void wave_run(const StackSeg* __restrict__ segs, int 
                 const uint4* hg = reinterpret_cast<const uint4*>(S.w16[3]);
 #pragma unroll
                 for (int st = 0; st < NK; ++st) wh[st][0] = ld_g(hg + st * 64 + lane);
-                hbias = gmem(S.bias[3])[col];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) hbias[k] = gmem(S.bias[3])[rowq + k];
             }
         }
         // ---- input rows (64 BF16 channels) and masked symbols of ring 0 ----
@@ -279,30 +287,31 @@ __device__ __forceinline__ void wave_run(const StackSeg* __restrict__ segs, int 
                 const int x = I.y0 - 3 - 2 * l + t;
                 const bool active = t >= 3 * l && t <= I.R + 5 + l;
                 auto write_row = [&](int xw) {
-                    // Output (position p, channel ch) goes to swz(1 + p, ch / 8) + (ch % 8) * 2;
-                    // block mb adds 16 slots (swizzle unchanged), so a lane needs one chunk
-                    // offset per (i, nb): ((2 (nb0 + nb) + col / 8) ^ ((1 + rowq + i) & 7)) * 16.
-                    // The lane index is made opaque to the loop optimiser here, so these
-                    // offsets are recomputed per row instead of being hoisted into registers.
+                    // Lane: position p = 16 mb + lane % 16, channels 16 (nb0 + nb) + 4 (lane / 16)
+                    // .. + 3, i.e. 8 bytes of chunk 2 (nb0 + nb) + lane / 32 at byte 8 ((lane / 16) & 1),
+                    // swizzled by slot 1 + p (block mb adds 16 slots: swizzle unchanged).  The lane
+                    // index is opaque to the loop optimiser here, so these offsets are recomputed
+                    // per row instead of being hoisted into registers.
                     int ln = lane;
                     asm volatile("" : "+v"(ln));
-                    const int wcol = ln & 15, wrowq = (ln >> 4) * 4;
-                    uint8_t* orow = rout + (xw & 3) * RROW + wrowq * PSTR + (wcol & 7) * 2;
+                    const int pm = ln & 15, sl = 1 + pm;
+                    uint8_t* orow = rout + (xw & 3) * RROW + sl * PSTR + ((ln >> 4) & 1) * 8;
                     const bool rok = xw >= 0 && xw < S.h;
 #pragma unroll
-                    for (int mb = 0; mb < 4; ++mb)
+                    for (int mb = 0; mb < 4; ++mb) {
+                        const int c = I.c0 - 3 + mb * 16 + pm;
+                        const bool ok = rok && c >= 0 && c < S.w;
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int c = I.c0 - 3 + mb * 16 + wrowq + i;
-                            const bool ok = rok && c >= 0 && c < S.w;
+                        for (int nb = 0; nb < NBL; ++nb) {
+                            float v[4];
 #pragma unroll
-                            for (int nb = 0; nb < NBL; ++nb) {
-                                const float val = fmaxf(acc[mb][nb][i] + bias[nb], 0.f);
-                                const int cofs = ((2 * (nb0 + nb) + (wcol >> 3)) ^ ((1 + wrowq + i) & 7)) * 16;
-                                *reinterpret_cast<uint16_t*>(orow + (1 + mb * 16 + i) * PSTR + cofs) =
-                                    ok ? f2bf(val) : (uint16_t)0;
-                            }
+                            for (int k = 0; k < 4; ++k) v[k] = fmaxf(acc[mb][nb][k] + bias[nb][k], 0.f);
+                            uint2 w = make_uint2(f2bf2(v[0], v[1]), f2bf2(v[2], v[3]));
+                            if (!ok) w = make_uint2(0u, 0u);
+                            const int chunk = 2 * (nb0 + nb) + (ln >> 5);
+                            *reinterpret_cast<uint2*>(orow + mb * 16 * PSTR + ((chunk ^ (sl & 7)) << 4)) = w;
                         }
+                    }
                 };
                 if (DEFER && pend) {
                     write_row(xpend);
@@ -331,8 +340,8 @@ __device__ __forceinline__ void wave_run(const StackSeg* __restrict__ segs, int 
 #pragma unroll
                     for (int mb = 0; mb < HEADM; ++mb)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            rg.head_st[(HEADM * HEADH + mb) * 16 + rowq + i][col] = acc[mb][0][i] + hbias;
+                        for (int k = 0; k < 4; ++k)
+                            rg.head_st[(HEADM * HEADH + mb) * 16 + col][rowq + k] = acc[mb][0][k] + hbias[k];
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
