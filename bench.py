@@ -66,6 +66,29 @@ def measured_traffic(precision):
     return TRAFFIC_BYTES_PER_LAUNCH.get(precision)
 
 
+# HBM bytes per launch of the fused step-stack kernel (steps 1-3) in the 64-image batch, from
+# rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0), the factors being what each counter reads for a
+# plain 1 GiB device copy; averaged over the 117 launches of three batch decodes.  Valid only for
+# the kernel source with this sha256 (else the line reports null).
+STACK_TRAFFIC_SOURCE = ("paper_2405_12631_amd/csrc/wv_stack_bf16.hip",
+                        "5fe37bc9cb528be5af10ef1eaf5090f5ae9debedb49cc9142834ce42393577cb")
+STACK_TRAFFIC_BYTES_PER_LAUNCH = 1968.67e6
+
+
+def measured_stack_traffic(args):
+    import hashlib
+    rel, digest = STACK_TRAFFIC_SOURCE
+    if digest is None or args.precision != "bf16":
+        return None
+    try:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    except OSError:
+        return None
+    return STACK_TRAFFIC_BYTES_PER_LAUNCH
+
+
 def _precision(name):
     from paper_2405_12631_amd import WV_BF16, WV_FP32, WV_FP8
     return {"fp32": WV_FP32, "bf16": WV_BF16, "fp8": WV_FP8}[name]
@@ -86,6 +109,15 @@ def context_flops_per_coef(cfg):
         cin = C if g == 0 else C + 1
         stacks += 9 * cin * C + (Lc - 2) * 9 * C * C + 9 * C * 3 * K / 4.0
     return 2.0 * (lstm + stacks)
+
+
+def stack_flops_per_coef(cfg, step):
+    """Algorithmic FLOPs of one coding step's conv stack per coefficient of the subband: every
+    layer but the head at all positions (the first with the symbol channel for step >= 1),
+    the 3K-output head at the quarter of positions the step codes."""
+    C, Lc, K = cfg["ctx_ch"], cfg["ctx_layers"], cfg["mix_k"]
+    cin = C if step == 0 else C + 1
+    return 2.0 * (9 * cin * C + (Lc - 2) * 9 * C * C + 9 * C * 3 * K / 4.0)
 
 
 def lifting_cost_per_px(cfg):
@@ -183,21 +215,31 @@ def bench_batch(args):
     # Stage times from one eager decode, each context-model call bracketed by events on
     # the launch stream.
     stream = torch.cuda.current_stream()
-    ev = []
+    ev, ev_cdf = {}, []
     for q in bt.q:
         codec.zero(q)
     for i in range(bt.nsub):
         for g in range(4):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
             e0.record(stream)
             prm = bt.context_params(i, g)
             e1.record(stream)
-            ev.append((e0, e1))
             bt.cdf_tables(prm)
+            e2.record(stream)
+            ev[(i, g)] = (e0, e1)
+            ev_cdf.append((e1, e2))
             bt.scatter(syms[i][g], i, g)
+    es0, es1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    es0.record(stream)
     bt.synthesize()
+    es1.record(stream)
     torch.cuda.synchronize()
-    ctx_s = sum(a.elapsed_time(b) for a, b in ev) * 1e-3
+    ctx_s = sum(a.elapsed_time(b) for a, b in ev.values()) * 1e-3
+    # Steps 1-3 of every subband launch only the fused step-stack kernel (step 0 also runs the
+    # ConvLSTM), so their event times are that kernel's launch times.
+    stk_s = sum(a.elapsed_time(b) for (i, g), (a, b) in ev.items() if g > 0) * 1e-3
+    cdf_s = sum(a.elapsed_time(b) for a, b in ev_cdf) * 1e-3
+    syn_s = es0.elapsed_time(es1) * 1e-3
     known = [q.clone() for q in bt.q]
     graph = bt.capture(syms)
     for _ in range(args.warmup):
@@ -219,8 +261,10 @@ def bench_batch(args):
     pixels = bt.pixels
     mpx = pixels * args.steps / elapsed / 1e6
     flops = context_flops_per_coef(cfg) * pixels * 3
+    stk_flops = sum(stack_flops_per_coef(cfg, g) for g in (1, 2, 3)) * pixels * 3
     peak = MFMA_PEAK_TFLOPS[args.precision]
-    nlaunch = bt.nsub * (cfg["ctx_layers"] * 4 + 1)     # per subband: the ConvLSTM and 4 step stacks
+    fused = args.precision == "bf16"
+    nlaunch = 3 * bt.nsub if fused else bt.nsub * (cfg["ctx_layers"] * 4 + 1)
     out = dict(
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
         value=round(mpx, 4), unit="Mpixel/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -236,13 +280,20 @@ def bench_batch(args):
         p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
         launch="one wv_graph replay per batch decode (captured once); context time and roofline from an "
                "event-bracketed eager pass of the same decode",
-        stage_ms=dict(context=round(ctx_s * 1e3, 3)),
-        roofline=dict(bound="mfma", achieved=round(flops / ctx_s / 1e12, 3), peak=peak, unit="TFLOP/s",
-                      frac=round(flops / ctx_s / 1e12 / peak, 4), traffic=None,
-                      kernel="conv3x3_mfma_bf16_seg (context model: ConvLSTM + step stacks, persistent "
-                             "plan launches)",
-                      flops_per_decode=flops, launches_per_decode=nlaunch,
-                      avg_launch_us=round(ctx_s / nlaunch * 1e6, 2)),
+        stage_ms=dict(context=round(ctx_s * 1e3, 3), step_stacks_1_3=round(stk_s * 1e3, 3),
+                      cdf=round(cdf_s * 1e3, 3), synthesis=round(syn_s * 1e3, 3)),
+        context_model=dict(tflop_per_s=round(flops / ctx_s / 1e12, 3), frac_of_peak=round(flops / ctx_s / 1e12 / peak, 4),
+                           flops_per_decode=flops,
+                           note="ConvLSTM + all step stacks, algorithmic FLOPs over the event-timed context calls"),
+        roofline=dict(bound="mfma", achieved=round(stk_flops / stk_s / 1e12, 3), peak=peak, unit="TFLOP/s",
+                      frac=round(stk_flops / stk_s / 1e12 / peak, 4), traffic=measured_stack_traffic(args),
+                      traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                      kernel=("stack_bf16_k<true> (fused step stacks of steps 1-3: three ReLU conv layers and "
+                              "the mixture head per launch)") if fused else
+                             "conv3x3_mfma_bf16_seg (step stacks of steps 1-3, layer by layer)",
+                      flops_per_decode=stk_flops, launches_per_decode=nlaunch,
+                      avg_launch_us=round(stk_s / nlaunch * 1e6, 2)),
+        stage_rates=stage_rates(cfg, pixels * 3, pixels * 3, cdf_s * 1e3, syn_s * 1e3),
     )
     # The first 256x256 image of the batch, for the CPU baseline.
     k = next(k for k, s_ in enumerate(sizes) if tuple(s_) == (256, 256))
