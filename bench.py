@@ -71,7 +71,7 @@ def measured_traffic(precision):
 # plain 1 GiB device copy; averaged over the 117 launches of three batch decodes.  Valid only for
 # the kernel source with this sha256 (else the line reports null).
 STACK_TRAFFIC_SOURCE = ("paper_2405_12631_amd/csrc/wv_stack_bf16.hip",
-                        "5fe37bc9cb528be5af10ef1eaf5090f5ae9debedb49cc9142834ce42393577cb")
+                        "caac903634ea7f485952e36b944733fcd610713c7d026a0aa39ceda22c722971")
 STACK_TRAFFIC_BYTES_PER_LAUNCH = 1968.67e6
 
 
@@ -308,7 +308,8 @@ def bench_serve(args):
     subband), BF16 context convs, admission by HBM footprint, continuous batching.
     Each request refers to one of a few prepared inputs (symbols on the device, the
     coder elided).  Runs the offered rate over the arrival window, a bisection for the
-    highest rate whose p99 stays stable, that rate over the full window, and the same
+    highest rate whose p99 stays stable, that rate confirmed over the full window (10 % lower
+    until it holds, at most three times), and the same
     arrivals through the host coder (tables trimmed and copied to the host, rANS on host
     threads); value = sustained Mpixel/s (luma pixels x frames for GOPs) under the offered
     rate."""
@@ -370,6 +371,7 @@ def bench_serve(args):
             runs[f"{r:g}_req_s"] = run(r, args.serve_seconds)
         hi = runs[f"{rates[0]:g}_req_s"]
         best = None
+        coder_rate = rates[0]
     else:
         hi = runs[f"{cfg['rate_hz']:g}_req_s"] = run(cfg["rate_hz"], args.serve_seconds)
         # Highest stable rate: bisection on shorter windows between a stable lower bound and
@@ -386,14 +388,23 @@ def bench_serve(args):
                 lo_r = mid
             else:
                 hi_r = mid
-        best = run(lo_r, args.serve_seconds)
+        # Confirm over the full window; a rate whose p99 still grows there is stepped down by
+        # 10 % (at most three times), and only a full-window stable run is reported as such.
+        best = None
+        for _ in range(4):
+            st = run(lo_r, args.serve_seconds)
+            runs[f"full_{lo_r:g}_req_s"] = st
+            log(f"confirm {lo_r} req/s over {args.serve_seconds:g} s: stable={st['stable']}")
+            if st["stable"]:
+                best = st
+                break
+            lo_r = round(lo_r * 0.9, 1)
+        coder_rate = best["rate_hz"] if best else st["rate_hz"]
         runs["search"] = search
-        runs[f"best_{lo_r:g}_req_s"] = best
     if args.serve_coder_seconds > 0:
         # The same arrivals through the host coder: tables trimmed on the device and copied to
         # the host every iteration, rANS decoding on host threads, symbols copied back.
-        crate = (best or hi)["rate_hz"]
-        runs[f"coder_{crate:g}_req_s"] = run(crate, args.serve_coder_seconds, coder=True)
+        runs[f"coder_{coder_rate:g}_req_s"] = run(coder_rate, args.serve_coder_seconds, coder=True)
     out = dict(
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
         value=hi["mpx_per_s"], unit="Mpixel/s", n_gpus=1, steps=hi["iterations"], warmup=0,

@@ -12,19 +12,21 @@
 // (64 BF16 channels per position).  Only the step's input l_i and the symbols
 // come from HBM and only the parameters of the step's positions go back.
 //
-// Work split (8 waves, two per SIMD; wave w runs on SIMD w mod 4).  The work of a row
-// step is 12 units (3 layers x 4 blocks of 16 output channels, 64 positions each) plus
-// the head (16 padded output columns) every other row and the input loads; each SIMD
-// gets three units:
-//   SIMD 0: wave 0 layer 0 blocks 0-1, wave 4 layer 0 block 2 and the input loads;
-//   SIMD 1: wave 1 layer 1 blocks 0-1, wave 5 layer 0 block 3;
-//   SIMD 2: wave 2 layer 2 blocks 0-1, wave 6 layer 1 block 2 and head positions 0-31;
-//   SIMD 3: wave 3 layer 2 blocks 2-3, wave 7 layer 1 block 3 and head positions 32-63.
+// Work split (8 waves, two per SIMD; wave w runs on SIMD w mod 4).  A row step is
+// 12 units of matrix work (3 layers x 4 blocks of 16 output channels, 64 positions
+// each), the head (16 padded output columns) on every other row, and the input loads:
+//   SIMD 0: wave 0 layer 0 blocks 0-1, wave 4 the head (all 64 positions) and its epilogue;
+//   SIMD 1: wave 1 layer 0 blocks 2-3, wave 5 the input rows and symbols of ring 0;
+//   SIMD 2: wave 2 layer 1 blocks 0-1, wave 6 layer 2 blocks 0-1;
+//   SIMD 3: wave 3 layer 1 blocks 2-3, wave 7 layer 2 blocks 2-3.
 // Each wave keeps its blocks' weight fragments in registers for the whole launch (72
 // VGPRs per block: 18 K steps of 32 input channels), so LDS carries only activations.
-// A row step ends with one workgroup barrier; layer l works 2 rows behind layer l - 1,
-// so all reads of a step see rows finished in earlier steps, and the ring slot a
-// layer writes is never one its consumer reads in the same step.
+// A row step ends with one LDS-only workgroup barrier.  In step t layer l computes row
+// y0 - 3 - 2 l + t (two rows behind layer l - 1), the loader stores input row y0 - 1 + t,
+// and the head computes row y0 - 10 + t; layer 2 writes its row in the step after the
+// one that computed it (its waves share SIMDs 2-3 with layer 1, and the deferred write
+// overlaps their MFMAs).  Every read of a step therefore sees rows finished in earlier
+// steps, and with 4-row rings no slot written in a step is one read in it.
 //
 // Bits: every output is accumulated with the same MFMA sequence as the
 // layer-by-layer kernel (taps 0..8, 32-channel chunks in order, the symbol
