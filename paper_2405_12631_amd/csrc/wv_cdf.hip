@@ -5,7 +5,7 @@
 // sym_min + j - 0.5, F_max = 2^16 - N_s; entry N_s (= 2^16) is stored as 0.
 // The exact value of the floor is produced:
 //   * outside [j_lo, j_hi], where every component is at least TZ scales away
-//     from the boundary (TZ = 6 Gaussian, 12 Laplace), the value is known
+//     from the boundary (TZ = 4.5 Gaussian, 11 Laplace), the value is known
 //     without evaluating Phi: C_j <= Phi(-TZ) < 1/F_max gives F_j = 0 below,
 //     and 0 < 1 - C_j < 1/F_max gives F_j = F_max - 1 above;
 //   * inside, the lower tail sum is used when C_j <= 1/2, else the upper tail
@@ -47,11 +47,19 @@ __global__ __launch_bounds__(ROWS * LPR) void cdf_k(const float* __restrict__ pa
     if (row < n) {
         CdfRow<K, DIST> R;
         cdf_setup<K, DIST>(params + row * (3 * K), smin, nsym, R);
-        for (int j = ja; j < jb; ++j) {
-            const int Fj = cdf_F<K, DIST>(R, j);
+        // The slice in three runs, each lane with its own bounds, so a wave steps through
+        // its longest window rather than the union of its rows' windows: F = 0 below the
+        // window, evaluated inside it (running maximum within the slice), F_max - 1 above.
+        const int j1 = min(max(R.jlo, ja), jb);
+        const int j2 = max(min(R.jhi + 1, jb), j1);
+        for (int j = ja; j < j1; ++j) my[j] = (uint16_t)(LPR > 1 ? 0 : j);
+        for (int j = j1; j < j2; ++j) {
+            const int Fj = cdf_F_in<K, DIST>(R, j);
             F = Fj > F ? Fj : F;
-            my[j] = (uint16_t)(LPR > 1 ? F : j + F);   // running maximum within the slice
+            my[j] = (uint16_t)(LPR > 1 ? F : j + F);
         }
+        if (j2 < jb) F = max(F, R.Fmax - 1);
+        for (int j = j2; j < jb; ++j) my[j] = (uint16_t)(LPR > 1 ? F : j + F);
     }
     if constexpr (LPR > 1) {
         // Maximum of F over the slices before this one: inclusive max-scan over the row's

@@ -66,7 +66,7 @@ __device__ __forceinline__ void mixture_head(const float* v, int K, float sigma_
 // parameters, then F_j before the running maximum.
 template <int K, int DIST>
 struct CdfRow {
-    float w[K], mu[K], sg[K];
+    float w[K], mu[K], rs[K];   // weights, means, reciprocal scales
     float invS;
     int jlo, jhi, Fmax, smin;
 };
@@ -80,18 +80,21 @@ __device__ __forceinline__ float tail_of(float az) {
 
 template <int K, int DIST>
 __device__ __forceinline__ void cdf_setup(const float* p, int smin, int nsym, CdfRow<K, DIST>& R) {
-    // Beyond TZ scales every component's tail is below 1/F_max: Gaussian 6
-    // (Phi(-6) = 1e-9), Laplace 12 (exp(-12)/2 = 3e-6).
-    constexpr float TZ = DIST == WV_DIST_GAUSS ? 6.0f : 12.0f;
+    // Beyond TZ scales every component's tail is below 1/F_max (F_max <= 2^16 - 2):
+    // Gaussian 4.5 (Phi(-4.5) = 3.4e-6, at most 0.23 counts), Laplace 11
+    // (exp(-11)/2 = 8.4e-6, at most 0.55 counts).  There floor(F_max C_j) is 0 below
+    // the window and the upper-tail form gives F_max - 1 above it.
+    constexpr float TZ = DIST == WV_DIST_GAUSS ? 4.5f : 11.0f;
     float S = 0.f, lo = 3.0e38f, hi = -3.0e38f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
+        const float sg = p[2 * K + k];
         R.w[k] = p[k];
         R.mu[k] = p[K + k];
-        R.sg[k] = p[2 * K + k];
+        R.rs[k] = 1.0f / sg;
         S += R.w[k];
-        lo = fminf(lo, R.mu[k] - TZ * R.sg[k]);
-        hi = fmaxf(hi, R.mu[k] + TZ * R.sg[k]);
+        lo = fminf(lo, R.mu[k] - TZ * sg);
+        hi = fmaxf(hi, R.mu[k] + TZ * sg);
     }
     R.invS = 1.0f / S;
     R.Fmax = 65536 - nsym;
@@ -103,15 +106,14 @@ __device__ __forceinline__ void cdf_setup(const float* p, int smin, int nsym, Cd
 
 // F_j = floor(F_max C_j) as in exact arithmetic (lower tail where C_j <= 1/2, else
 // F_max - ceil(F_max (1 - C_j)) with at least one count below F_max).
+// Inside the window (jlo <= j <= jhi).
 template <int K, int DIST>
-__device__ __forceinline__ int cdf_F(const CdfRow<K, DIST>& R, int j) {
-    if (j < R.jlo) return 0;
-    if (j > R.jhi) return R.Fmax - 1;
+__device__ __forceinline__ int cdf_F_in(const CdfRow<K, DIST>& R, int j) {
     const float b = (float)(R.smin + j) - 0.5f;
     float L = 0.f, U = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const float z = (b - R.mu[k]) / R.sg[k];
+        const float z = (b - R.mu[k]) * R.rs[k];
         const float tail = tail_of<DIST>(fabsf(z));
         if (z < 0.f) {
             L = fmaf(R.w[k], tail, L);
@@ -126,6 +128,13 @@ __device__ __forceinline__ int cdf_F(const CdfRow<K, DIST>& R, int j) {
     if (L <= U) return (int)floorf((float)R.Fmax * L);
     const int up = (int)ceilf((float)R.Fmax * U);
     return R.Fmax - (up < 1 ? 1 : up);
+}
+
+template <int K, int DIST>
+__device__ __forceinline__ int cdf_F(const CdfRow<K, DIST>& R, int j) {
+    if (j < R.jlo) return 0;
+    if (j > R.jhi) return R.Fmax - 1;
+    return cdf_F_in<K, DIST>(R, j);
 }
 
 }  // namespace wv

@@ -301,6 +301,18 @@ hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecL
                              hipStream_t s) {
     if ((long long)N * h * w == 0) return hipSuccess;
     if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2) {
+        // Arrays of at least LIFT_ROWS_MIN_STRIP_ROWS strip rows whose width the 124-column
+        // strips cover with at most 8 % to spare stream rows (wv_lift_rows.hip): measured on
+        // 64-image batches, 1088 x 1920 synthesis 13 % faster (960-, 480-, 240-, 120-column
+        // arrays), while 512- and 384-column arrays (5 and 4 strips, the last one nearly empty)
+        // were 20-30 % slower than the tiles.  WV_LIFT_FORM=tile / rows forces one form (tests
+        // compare them bit for bit).
+        const char* env = getenv("WV_LIFT_FORM");
+        const bool force_tile = env && env[0] == 't', force_rows = env && env[0] == 'r';
+        const long long nstrips = (w + LIFT_ROWS_OUTW - 1) / LIFT_ROWS_OUTW;
+        const bool covers = nstrips * LIFT_ROWS_OUTW * 100 <= (long long)w * 108;
+        if (force_rows || (!force_tile && covers && nstrips * N * h >= LIFT_ROWS_MIN_STRIP_ROWS))
+            return launch_lift_rows(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s);
         // The 16 x 32 tile needs one 8-wave workgroup per CU, whose phases (vector layer 1, MFMA
         // layer 2, layer 3) no longer overlap with a second workgroup's; it pays off only where
         // its lower recompute has many rounds of tiles to work on (measured: 1088 x 1920 planes

@@ -604,3 +604,32 @@ def test_lifting_tile_forms_bitwise_ragged():
     x12, _ = codec.synthesize(model, ws12, q=q12)
     x3, _ = codec.synthesize(model, ws3, q=q3)
     assert torch.equal(x12[:3], x3)
+
+
+@pytest.mark.parametrize("H,W,planes", [(512, 768, 3), (528, 784, 2), (1088, 1920, 1), (48, 80, 3)])
+def test_lifting_row_form_bitwise(H, W, planes):
+    """The row-streaming lifting kernel (taken for large arrays) forced on every filter
+    launch of analysis and synthesis, against the tiled kernel forced likewise: the same
+    coefficients, symbols and reconstruction, bit for bit.  Covers ragged 126-column strips
+    (392, 784 and 960 columns), ragged row segments, and arrays smaller than one strip (the
+    coarse levels, and 48 x 80)."""
+    import os
+    need_gpu()
+    from paper_2405_12631_amd import codec
+    say("lifting row form", H, W, planes)
+    cfg = get_config("ycbcr512x768")
+    model, _ = model_for(cfg)
+    x = torch.from_numpy(sinusoid_1f_planes(H, W, planes=planes, seed=21)).cuda()
+    ws = codec.Workspace(model, planes, H, W)
+    res = {}
+    for form in ("tile", "rows"):
+        os.environ["WV_LIFT_FORM"] = form
+        try:
+            q, y, _ = codec.analyze(model, x, ws, want_y=True)
+            xh, _ = codec.synthesize(model, ws, q=q)
+            torch.cuda.synchronize()
+            res[form] = (q.clone(), y.clone(), xh.clone())
+        finally:
+            del os.environ["WV_LIFT_FORM"]
+    for name, a, b in zip(("q", "y", "xhat"), res["tile"], res["rows"]):
+        assert torch.equal(a, b), name
