@@ -173,7 +173,8 @@ def test_plan_decode_matches_oracle_fp32():
     group's parameters (plane 0) against the FP64 oracle on the same symbols, at every
     (subband, step) (for 1088 x 1920 the level-4 and level-3 subbands, whose oracle finishes in
     seconds), one step's CDF rows against the oracle's tables of those parameters, and every
-    group's reconstruction (plane 0; the 1088 x 1920 planes take the 16 x 32 lifting tile)."""
+    group's reconstruction (plane 0; the wide 1088 x 1920 arrays take the row-streaming lifting
+    kernel, the others the tiles)."""
     need_gpu()
     from paper_2405_12631_amd import codec, batch as B
     say("plan vs oracle fp32")
