@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libwv.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["wv_api.hip", "wv_conv.hip", "wv_conv_bf16.hip", "wv_lift.hip", "wv_cdf.hip",
-               "wv_ar.hip", "wv_lift_fused.hip", "wv_stack_bf16.hip", "wv_lift_rows.hip"]
+               "wv_ar.hip", "wv_lift_fused.hip", "wv_stack_bf16.hip", "wv_lift_rows.hip", "wv_lstm_bf16.hip"]
 CXX_SOURCES = ["wv_rans.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1332,7 +1332,7 @@ struct PlanLaunch {
     long long total;     // work items
     MfmaLayer proto;
     MfmaLayer16 proto16;
-    int fused = 0;       // 1: a whole step stack in one launch (StackSeg array)
+    int fused = 0;       // 1: a whole step stack in one launch (StackSeg array); 2: the ConvLSTM (LstmSeg)
     int has_sym = 0;
 };
 
@@ -1387,6 +1387,40 @@ long long make_stack_seg(const wv_model* m, int type, int g, const float* hcur, 
     }
     return (long long)sg.strips_x * sg.segs_y * nplanes;
 }
+
+// Segment of a fused ConvLSTM launch for subband S of a plane group whose ConvLSTM state
+// halves start at d_state (SS floats each: h then c), symbols at q (plane stride q_ps);
+// Pv is the previous subband (null for the first).  Returns the segment's work items.
+long long make_lstm_seg(const wv_model* m, int i, const Sub& S, const Sub* Pv, float* d_state, size_t SS,
+                        int nplanes, const int16_t* q, long long q_ps, long long item0, LstmSeg& sg) {
+    const int C = m->cfg.ctx_ch;
+    sg = LstmSeg{};
+    sg.wt = m->lstm16.w;
+    sg.wsym = m->lstm16.wsym;
+    sg.bias = m->lstm16.bias;
+    float* hcur = d_state + (size_t)(i & 1) * 2 * SS;
+    if (Pv) {
+        float* hold = d_state + (size_t)((i - 1) & 1) * 2 * SS;
+        sg.up = (S.h == 2 * Pv->h) ? 1 : 0;
+        sg.in16 = reinterpret_cast<const uint16_t*>(hold);
+        sg.in_ps = (long long)Pv->h * Pv->w * C;
+        sg.sym = q + Pv->off;
+        sg.sym_ps = q_ps;
+        sg.c_prev = hold + SS;
+        sg.cprev_ps = (long long)Pv->h * Pv->w * C;
+    }
+    sg.h_out = reinterpret_cast<uint16_t*>(hcur);
+    sg.c_out = hcur + SS;
+    sg.st_ps = (long long)S.h * S.w * C;
+    sg.N = nplanes;
+    sg.h = S.h;
+    sg.w = S.w;
+    sg.strips_x = (S.w + LSTM_STRIP - 1) / LSTM_STRIP;
+    sg.seg_rows = stack_seg_rows(S.h);
+    sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
+    sg.item0 = item0;
+    return (long long)sg.strips_x * sg.segs_y * nplanes;
+}
 }  // namespace
 
 struct wv_plan {
@@ -1435,8 +1469,31 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
             const int level = P->lay[0][i].level;
             const int nlayers = (int)(bf16 ? m->ctx16[type][g].size() : m->ctx[type][g].size());
             const bool fuse = stack_fusable(m);
-            // launch list: LSTM at step 0, then the stack's layers (or the fused stack)
-            for (int l = (g == 0 ? -1 : 0); l < (fuse ? 0 : nlayers); ++l) {
+            // launch list: LSTM at step 0, then the stack's layers (or the fused ConvLSTM and
+            // the fused stack)
+            if (fuse && g == 0) {
+                PlanLaunch pl{};
+                host.resize((host.size() + 255) & ~(size_t)255);
+                pl.seg_off = host.size();
+                pl.nseg = ng;
+                pl.fused = 2;
+                long long item = 0;
+                for (int b = 0; b < ng; ++b) {
+                    const wv_group& G = groups[b];
+                    LstmSeg sg;
+                    item += make_lstm_seg(m, i, P->lay[b][i], i > 0 ? &P->lay[b][i - 1] : nullptr, G.d_state,
+                                          state_floats(m->cfg, G.nplanes, G.H, G.W), G.nplanes, G.d_q,
+                                          (long long)G.H * G.W, item, sg);
+                    const size_t at = host.size();
+                    host.resize(at + sizeof(LstmSeg));
+                    memcpy(host.data() + at, &sg, sizeof sg);
+                }
+                pl.total = item;
+                pl.grid = (int)(item < 256 ? item : 256);
+                P->steps[i * 4].push_back(pl);
+                host.resize((host.size() + 255) & ~(size_t)255);
+            }
+            for (int l = (g == 0 && !fuse ? -1 : 0); l < (fuse ? 0 : nlayers); ++l) {
                 const bool lstm = l < 0;
                 const bool last = l == nlayers - 1;
                 const int mode = lstm ? CONV_LSTM : (last ? CONV_HEAD : CONV_RELU);
@@ -1650,6 +1707,11 @@ static int plan_step_launch(const wv_plan* p, int i, int g, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const bool bf16 = p->m->precision != WV_FP32;   // BF16 or FP8 kernels
     for (const PlanLaunch& pl : p->steps[i * 4 + g]) {
+        if (pl.fused == 2) {
+            HIPCHK(launch_lstm_bf16(reinterpret_cast<const LstmSeg*>(p->d_desc + pl.seg_off), pl.nseg, pl.total,
+                                    pl.grid, s));
+            continue;
+        }
         if (pl.fused) {
             HIPCHK(launch_stack_bf16(reinterpret_cast<const StackSeg*>(p->d_desc + pl.seg_off), pl.nseg, pl.total,
                                      pl.has_sym, pl.grid, s));
@@ -1686,7 +1748,7 @@ namespace {
 struct ItemLaunch {
     std::vector<char> segs;
     int nseg = 0, mode = 0, nb = 1;
-    int fused = 0, has_sym = 0;   // fused step stacks: segs holds StackSeg
+    int fused = 0, has_sym = 0;   // 1: fused step stacks (segs holds StackSeg); 2: fused ConvLSTM (LstmSeg)
     long long total = 0;
     long long tiles = 0;
     MfmaLayer proto{};
@@ -1750,6 +1812,7 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     launches[fuse0 + 1].fused = 1;
     launches[fuse0 + 1].has_sym = 1;
     launches[0].mode = CONV_LSTM;
+    if (fuse) launches[0].fused = 2;   // the fused ConvLSTM (LstmSeg array)
     launches[1].mode = CONV_RELU;
     launches[2].mode = CONV_RELU;
     for (int l = 1; l < Lc - 1; ++l) launches[2 + l].mode = CONV_RELU;
@@ -1784,7 +1847,16 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
         base.w = S.w;
         base.tiles_x = (S.w + tw - 1) / tw;
         base.tiles_y = (S.h + th - 1) / th;
-        if (g == 0) {
+        if (g == 0 && fuse) {
+            ItemLaunch& Ll = launches[0];
+            LstmSeg sg;
+            Ll.total += make_lstm_seg(m, i, S, i > 0 ? &lay[i - 1] : nullptr, it.d_state, SS, it.nplanes, it.d_q, HW,
+                                      Ll.total, sg);
+            const size_t at = Ll.segs.size();
+            Ll.segs.resize(at + sizeof(LstmSeg));
+            memcpy(Ll.segs.data() + at, &sg, sizeof sg);
+            Ll.nseg++;
+        } else if (g == 0) {
             ConvArgs a = base;
             a.sym_step = 4;
             a.h_out = hcur;
@@ -1880,6 +1952,11 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     for (size_t r = 0; r < launches.size(); ++r) {
         const ItemLaunch& Lx = launches[r];
         if (!Lx.nseg || !Lx.total) continue;
+        if (Lx.fused == 2) {
+            HIPCHK(launch_lstm_bf16(reinterpret_cast<const LstmSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
+                                    (int)(Lx.total < 256 ? Lx.total : 256), s));
+            continue;
+        }
         if (Lx.fused) {
             HIPCHK(launch_stack_bf16(reinterpret_cast<const StackSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
                                      Lx.has_sym, (int)(Lx.total < 256 ? Lx.total : 256), s));

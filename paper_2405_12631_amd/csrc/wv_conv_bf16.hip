@@ -402,7 +402,7 @@ __device__ __forceinline__ void conv_tile_bf16(const MfmaLayer16& L, const ConvA
                     const float gf = sigmoid_fast(fmaf(acc[mb][1][i], csc[1 % NB], bf));
                     const float gg = tanh_fast(fmaf(acc[mb][2][i], csc[2 % NB], bg));
                     const float go = sigmoid_fast(fmaf(acc[mb][3][i], csc[3 % NB], bo));
-                    const float cn = gf * cp[mb][i] + gi * gg;
+                    const float cn = fmaf(gf, cp[mb][i], gi * gg);   // one rounding order for every LSTM kernel
                     const float hn = go * tanh_fast(cn);
                     const long long o = (long long)n * a.st_ps + ((long long)r * a.w + c) * a.C + ch;
                     c_out[o] = cn;

@@ -158,6 +158,29 @@ struct StackSeg {
 };
 constexpr int STACK_STRIP = 58;   // output columns per strip
 
+// One segment of a fused ConvLSTM launch (wv_lstm_bf16.hip): a plane group's subband at
+// step 0.  Gates = conv3x3([q of the previous subband, h of the previous subband]) with the
+// packed BF16 LSTM layer; inputs read at (r >> up, c >> up) when the resolution doubled.
+// Work items: planes x vertical segments of seg_rows rows x strips of LSTM_STRIP columns.
+struct LstmSeg {
+    const uint16_t* wt;     // packed weights [tap][32-channel chunk][16-column block][64 lanes] (uint4)
+    const uint16_t* wsym;   // symbol-channel weights [block][64 lanes] (uint4)
+    const float* bias;      // [256] in packed column order
+    const uint16_t* in16;   // h of the previous subband, NHWC BF16, or null (zeros)
+    long long in_ps;
+    const int16_t* sym;     // symbols of the previous subband (plane 0, packed layout), or null
+    long long sym_ps;
+    const float* c_prev;    // c of the previous subband, NHWC FP32, or null
+    long long cprev_ps;
+    uint16_t* h_out;        // NHWC BF16 [N][h][w][64]
+    float* c_out;           // NHWC FP32
+    long long st_ps;
+    int N, h, w, up;        // up: inputs at half resolution (nearest x2)
+    int strips_x, segs_y, seg_rows;
+    long long item0;
+};
+constexpr int LSTM_STRIP = 64;   // output columns per strip
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_conv(const MfmaLayer& L, int mode, const ConvArgs& a, hipStream_t s);
 hipError_t launch_conv_bf16(const MfmaLayer16& L, int mode, const ConvArgs& a, hipStream_t s);
@@ -170,6 +193,8 @@ hipError_t launch_conv_seg_bf16(const ConvSeg16* segs, int nseg, long long total
 // Fused BF16 step stacks over device segment arrays (has_sym: every segment has step >= 1).
 hipError_t launch_stack_bf16(const StackSeg* segs, int nseg, long long total, int has_sym, int grid,
                              hipStream_t s);
+// Fused BF16 ConvLSTM over device segment arrays.
+hipError_t launch_lstm_bf16(const LstmSeg* segs, int nseg, long long total, int grid, hipStream_t s);
 // Output blocks per workgroup chosen for a launch of `tiles` position tiles.
 int conv_pick_nb(int nbt, int mode, long long tiles, int lowp);
 int conv_tile_h(int bf16);

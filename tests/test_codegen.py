@@ -18,8 +18,8 @@ from paper_2405_12631_amd import build as B
 
 HIPCC = B.HIPCC
 SOURCES = ["wv_conv.hip", "wv_conv_bf16.hip", "wv_lift_fused.hip", "wv_lift.hip", "wv_cdf.hip",
-           "wv_stack_bf16.hip", "wv_lift_rows.hip"]
-FLAT_FREE = ("conv3x3", "lift_fused_k", "stack_bf16_k", "lift_rows_k")
+           "wv_stack_bf16.hip", "wv_lift_rows.hip", "wv_lstm_bf16.hip"]
+FLAT_FREE = ("conv3x3", "lift_fused_k", "stack_bf16_k", "lift_rows_k", "lstm_bf16_k")
 
 
 def _kernels(asm):

@@ -223,11 +223,12 @@ def test_plan_decode_matches_oracle_fp32():
 
 
 def test_fused_step_stacks_equal_layer_by_layer_bitwise():
-    """The fused BF16 step-stack kernel (one launch per step: three ReLU layers and the head
-    with activations in LDS) against the layer-by-layer launches, bit for bit, on every
-    (subband, step) of a plan with tall subbands split into row pieces (1088 x 1920: level 1 is
-    544 rows in five pieces, 17 strips with a ragged last one), a 256 x 256 image and a small
-    ragged one."""
+    """The fused BF16 kernels (the ConvLSTM with weights in registers and input rows in an LDS
+    ring; the step stacks: three ReLU layers and the head with activations in LDS) against the
+    layer-by-layer launches, bit for bit: the parameters of every (subband, step) and the
+    ConvLSTM's h and c after every subband, on a plan with tall subbands split into row pieces
+    (1088 x 1920: level 1 is 544 rows in five pieces, 17 stack strips with a ragged last one),
+    a 256 x 256 image and a small ragged one."""
     import os
     need_gpu()
     from paper_2405_12631_amd import codec, batch as B, WV_BF16
@@ -244,8 +245,17 @@ def test_fused_step_stacks_equal_layer_by_layer_bitwise():
     fused = B.Batch(model, sizes)
     layered.load_images(imgs)
     fused.load_images(imgs)
+    C = cfg["ctx_ch"]
     for i in range(fused.nsub):
         for g in range(4):
             a = fused.context_params(i, g)
             b = layered.context_params(i, g)
             assert torch.equal(a, b), (i, g)
+            if g == 0:   # the state half of subband i: h (BF16) then, SS floats on, c (FP32)
+                for wf, wl in zip(fused.ws, layered.ws):
+                    lay = wf.lay[i]
+                    n = wf.N * lay["h"] * lay["w"] * C
+                    SS = wf.state.numel() // 4
+                    h0, c0 = (i & 1) * 2 * SS, (i & 1) * 2 * SS + SS
+                    assert torch.equal(wf.state[h0:h0 + n // 2], wl.state[h0:h0 + n // 2]), ("h", i)
+                    assert torch.equal(wf.state[c0:c0 + n], wl.state[c0:c0 + n]), ("c", i)
