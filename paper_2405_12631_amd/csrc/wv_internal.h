@@ -232,13 +232,13 @@ hipError_t launch_ar_params(const ArModel& M, const int16_t* q, long long q_ps, 
 hipError_t launch_ar_decode(const ArModel& M, const ArStreams& S, int16_t* q, long long q_ps, int h,
                             int w, int N, int smin, int nsym, int* status, hipStream_t s);
 // A whole three-layer predict/update filter and its lifting update in one kernel.
-// Row-streaming form for 32-channel filters (wv_lift_rows.hip): strips of LIFT_ROWS_OUTW
-// output columns; launch_lift_fused takes it for arrays of at least
-// LIFT_ROWS_MIN_STRIP_ROWS (strip x row) units.
+// Row-streaming form for 32-channel filters (wv_lift_rows.hip): the first `nstrips` strips of
+// LIFT_ROWS_OUTW output columns (the last one may be partial); launch_lift_fused takes it for
+// arrays of at least LIFT_ROWS_MIN_STRIP_ROWS (strip x row) units.
 constexpr int LIFT_ROWS_OUTW = 124;
 constexpr long long LIFT_ROWS_MIN_STRIP_ROWS = 2048;
 hipError_t launch_lift_rows(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A, View out,
-                            int N, int h, int w, int predict, float sign, int lift_int, hipStream_t s);
+                            int N, int h, int w, int nstrips, int predict, float sign, int lift_int, hipStream_t s);
 hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A,
                              View out, int N, int h, int w, int predict, float sign, int lift_int,
                              hipStream_t s);

@@ -28,8 +28,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 template <int C, int OH, int OW, int NWV>
 __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, const MfmaLayer L2, const VecLayer L3,
                                                         const CView z, const CView A, const View out, int N,
-                                                        int h, int w, int tiles_x, int tiles_y, int predict,
-                                                        float sign, int lift_int, int total) {
+                                                        int h, int w, int tiles_x, int tiles_y, int cbeg,
+                                                        int predict, float sign, int lift_int, int total) {
     constexpr int NT = 64 * NWV;            // threads
     constexpr int ZH = OH + 6, ZW = OW + 6;   // z halo
     constexpr int AH = OH + 4, AW = OW + 4;   // first layer region
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
         const int ty = t % tiles_y;
         T.n = t / tiles_y;
         T.r0 = ty * OH;
-        T.c0 = tx * OW;
+        T.c0 = cbeg + tx * OW;
         return T;
     };
     // z halo of a tile, NZ positions per thread
@@ -283,14 +283,14 @@ long long lift_resident() {
 
 template <int C, int OH, int OW, int NWV>
 hipError_t lift_launch(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A, View out, int N,
-                       int h, int w, int predict, float sign, int lift_int, hipStream_t s) {
-    const int tx = (w + OW - 1) / OW, ty = (h + OH - 1) / OH;
+                       int h, int w, int predict, float sign, int lift_int, hipStream_t s, int cbeg = 0) {
+    const int tx = (w - cbeg + OW - 1) / OW, ty = (h + OH - 1) / OH;
     const long long total = (long long)tx * ty * N;
     if (total >= (1ll << 31)) return hipErrorInvalidValue;
     const long long res = lift_resident<C, OH, OW, NWV>();
     const long long g = total < res ? total : res;
     hipLaunchKernelGGL((lift_fused_k<C, OH, OW, NWV>), dim3((unsigned)g), dim3(64 * NWV), 0, s, L1, L2, L3, z, A, out,
-                       N, h, w, tx, ty, predict, sign, lift_int, (int)total);
+                       N, h, w, tx, ty, cbeg, predict, sign, lift_int, (int)total);
     return hipGetLastError();
 }
 
@@ -301,18 +301,26 @@ hipError_t launch_lift_fused(const VecLayer& L1, const MfmaLayer& L2, const VecL
                              hipStream_t s) {
     if ((long long)N * h * w == 0) return hipSuccess;
     if (L1.ch == 32 && L2.cin == 32 && L2.nbt == 2) {
-        // Arrays of at least LIFT_ROWS_MIN_STRIP_ROWS strip rows whose width the 124-column
-        // strips cover with at most 8 % to spare stream rows (wv_lift_rows.hip): measured on
-        // 64-image batches, 1088 x 1920 synthesis 13 % faster (960-, 480-, 240-, 120-column
-        // arrays), while 512- and 384-column arrays (5 and 4 strips, the last one nearly empty)
-        // were 20-30 % slower than the tiles.  WV_LIFT_FORM=tile / rows forces one form (tests
+        // Wide arrays stream rows (wv_lift_rows.hip) in 124-column strips; a last strip that
+        // would be less than 70 % used is left to the tiles as a band of the remaining columns
+        // (a whole strip costs the same however much of it is used).  Measured on the 64-image
+        // batch: 1088 x 1920 arrays (960-, 480-, 240-, 120-column: last strips 74-97 % used) 13 %
+        // faster in rows than in tiles; 512- and 384-column arrays 20-30 % slower in rows alone
+        // (last strips 13 % and 10 % used), and with the band the batch's lifting went from
+        // 115.3 to 110.9 ms.  WV_LIFT_FORM=tile / rows forces one form where it applies (tests
         // compare them bit for bit).
         const char* env = getenv("WV_LIFT_FORM");
         const bool force_tile = env && env[0] == 't', force_rows = env && env[0] == 'r';
-        const long long nstrips = (w + LIFT_ROWS_OUTW - 1) / LIFT_ROWS_OUTW;
-        const bool covers = nstrips * LIFT_ROWS_OUTW * 100 <= (long long)w * 108;
-        if (force_rows || (!force_tile && covers && nstrips * N * h >= LIFT_ROWS_MIN_STRIP_ROWS))
-            return launch_lift_rows(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s);
+        const int full = w / LIFT_ROWS_OUTW, rem = w - full * LIFT_ROWS_OUTW;
+        const bool partial = 10 * rem >= 7 * LIFT_ROWS_OUTW;   // the last strip in rows too
+        const int nrows = full + (partial ? 1 : 0);              // strips in rows
+        if (!force_tile && nrows > 0 &&
+            (force_rows || (long long)nrows * N * h >= LIFT_ROWS_MIN_STRIP_ROWS)) {
+            hipError_t e = launch_lift_rows(L1, L2, L3, z, A, out, N, h, w, nrows, predict, sign, lift_int, s);
+            if (e != hipSuccess || partial || rem == 0) return e;
+            return lift_launch<32, 8, 16, 4>(L1, L2, L3, z, A, out, N, h, w, predict, sign, lift_int, s,
+                                             full * LIFT_ROWS_OUTW);
+        }
         // The 16 x 32 tile needs one 8-wave workgroup per CU, whose phases (vector layer 1, MFMA
         // layer 2, layer 3) no longer overlap with a second workgroup's; it pays off only where
         // its lower recompute has many rounds of tiles to work on (measured: 1088 x 1920 planes

@@ -338,8 +338,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void l
 // rounds of the resident workgroups as its items need, so the number of row segments is the
 // one that minimises rounds x (rows per segment + 10).
 hipError_t launch_lift_rows(const VecLayer& L1, const MfmaLayer& L2, const VecLayer& L3, CView z, CView A, View out,
-                            int N, int h, int w, int predict, float sign, int lift_int, hipStream_t s) {
-    if ((long long)N * h * w == 0) return hipSuccess;
+                            int N, int h, int w, int nstrips, int predict, float sign, int lift_int, hipStream_t s) {
+    if ((long long)N * h * w == 0 || nstrips == 0) return hipSuccess;
+    if (nstrips < 0 || (long long)(nstrips - 1) * OUTW >= w) return hipErrorInvalidValue;
     if (L1.ch != LC || L2.cin != LC || L2.nbt != 2) return hipErrorInvalidValue;
     static int resident = 0;
     if (resident == 0) {
@@ -350,7 +351,6 @@ hipError_t launch_lift_rows(const VecLayer& L1, const MfmaLayer& L2, const VecLa
             return hipErrorInvalidValue;
         resident = per_cu * cus;
     }
-    const int nstrips = (w + OUTW - 1) / OUTW;
     const long long cols = (long long)nstrips * N;
     int seg_rows = h;
     long long best = -1;
