@@ -5,11 +5,11 @@ batch-1 path, on one GPU.
 Default line (the headline): one step = one coder-elided decode of a batch of
 64 three-plane images of uneven size (256x256, 512x768, 1024x1024, 1088x1920;
 seed 3) with BF16 context convs: for each of the 13 subbands x 4 coding steps
-one persistent launch per layer over all images, the CDF tables of the step in
-one launch, the scatter of that step's symbols (the symbols the host entropy
-coder would return are taken from a device buffer), then synthesis; the whole
-decode replayed as one library graph, channel blocking autotuned before
-timing.  In the same process the plain FP32 batch-1 decode of the 512x768x3
+one persistent launch over all images (the fused ConvLSTM at step 0, then the
+fused step stack), the CDF tables of the step in one launch, the scatter of
+that step's symbols (the symbols the host entropy coder would return are taken
+from a device buffer), then synthesis; the whole decode replayed as one library
+graph.  In the same process the plain FP32 batch-1 decode of the 512x768x3
 image is measured the same way; vs_baseline = headline Mpixel/s / FP32
 batch-1 Mpixel/s, and the FP32 line is nested as "baseline".  Inputs are
 resident in HBM before timing.
@@ -20,8 +20,9 @@ resident in HBM before timing.
                                 precision_report|coder512x768|hbm_copy]
 
 --workload ycbcr512x768 prints the single-image line alone (FP32 unless
---precision), batch64_mixed the batch line alone; --nb-table fixes the batch's
-per-level channel blocking (no autotuning, e.g. for a profiled run);
+--precision), batch64_mixed the batch line alone; the layer-by-layer batch
+forms (FP32, FP8, or WV_FUSED_STACKS=0) autotune their per-level channel
+blocking before timing, and --nb-table fixes it (e.g. for a profiled run);
 serve_mix runs the continuous-batching server under Poisson arrivals.
 
 Prints one JSON line.
@@ -190,7 +191,8 @@ def cpu_baseline(cfg, w, q_planes, H, W):
 def bench_batch(args):
     """Mixed-size batch: 64 three-plane images from four sizes (seed 3), reduced-precision
     context convs, one plan (persistent launches), the whole decode captured as one library
-    graph, per-level blocking autotuned before timing (or fixed by --nb-table).  One step =
+    graph; the layer-by-layer forms' per-level blocking autotuned before timing (or fixed by
+    --nb-table), the fused BF16 kernels have none.  One step =
     one graph replay = one coder-elided decode of all 64 images.  Returns the line's dict,
     and the batch and one 256x256 image's symbols for the CPU baseline."""
     import torch
@@ -207,9 +209,13 @@ def bench_batch(args):
     del images
     syms = bt.known_symbols()
     log = (lambda m: print(m, file=sys.stderr, flush=True))
+    # BF16 plans run the fused ConvLSTM and step-stack kernels, which have no channel blocking.
+    fused = args.precision == "bf16" and os.environ.get("WV_FUSED_STACKS", "1") != "0"
     if args.nb_table:
         tab = [int(v) for v in args.nb_table.split(",")]
         bt.replan(tab)
+    elif fused:
+        tab = None
     else:
         tab, _ = B.autotune(bt, syms, reps=1, log=log)
     # Stage times from one eager decode, each context-model call bracketed by events on
@@ -263,7 +269,6 @@ def bench_batch(args):
     flops = context_flops_per_coef(cfg) * pixels * 3
     stk_flops = sum(stack_flops_per_coef(cfg, g) for g in (1, 2, 3)) * pixels * 3
     peak = MFMA_PEAK_TFLOPS[args.precision]
-    fused = args.precision == "bf16"
     nlaunch = 3 * bt.nsub if fused else bt.nsub * (cfg["ctx_layers"] * 4 + 1)
     out = dict(
         metric="decoded Mpixel/s (ctx model+CDF+inverse lifting), p50/p99 latency vs plain FP32",
@@ -275,7 +280,9 @@ def bench_batch(args):
                              f"{[list(s_) for s_ in cfg['sizes']]} (seed 3), 1/f sinusoids + noise, 4-level "
                              f"CNN lifting (32 ch), 64-ch 4-layer context stacks, K=3 mixture, step 4, "
                              f"{args.precision.upper()} context convs, one plan (persistent launches) "
-                             f"replayed as one library graph, channel blocking {tab}, coder elided",
+                             "replayed as one library graph, " +
+                             ("fused ConvLSTM and step-stack kernels" if fused else f"channel blocking {tab}") +
+                             ", coder elided",
                     batch=cfg["batch"], pixels=pixels, planes=3),
         p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
         launch="one wv_graph replay per batch decode (captured once); context time and roofline from an "
