@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -1336,6 +1337,20 @@ struct PlanLaunch {
     int has_sym = 0;
 };
 
+// Compute units of the current device, cached per device: the grid of the persistent fused
+// launches, which keep one workgroup per compute unit.
+int device_cus() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cache[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 // Whether a model's step stacks can run as one fused launch per step (wv_stack_bf16.hip):
 // BF16, 64 channels, three ReLU layers and the head, the head's 3K outputs in one
 // 16-column block.  WV_FUSED_STACKS=0 keeps the layer-by-layer launches (tests compare
@@ -1489,7 +1504,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                     memcpy(host.data() + at, &sg, sizeof sg);
                 }
                 pl.total = item;
-                pl.grid = (int)(item < 256 ? item : 256);
+                pl.grid = (int)std::min<long long>(item, device_cus());
                 P->steps[i * 4].push_back(pl);
                 host.resize((host.size() + 255) & ~(size_t)255);
             }
@@ -1621,7 +1636,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                     memcpy(host.data() + at, &sg, sizeof sg);
                 }
                 pl.total = item;
-                pl.grid = (int)(item < 256 ? item : 256);
+                pl.grid = (int)std::min<long long>(item, device_cus());
                 P->steps[i * 4 + g].push_back(pl);
                 host.resize((host.size() + 255) & ~(size_t)255);
             }
@@ -1954,12 +1969,12 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
         if (!Lx.nseg || !Lx.total) continue;
         if (Lx.fused == 2) {
             HIPCHK(launch_lstm_bf16(reinterpret_cast<const LstmSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
-                                    (int)(Lx.total < 256 ? Lx.total : 256), s));
+                                    (int)std::min<long long>(Lx.total, device_cus()), s));
             continue;
         }
         if (Lx.fused) {
             HIPCHK(launch_stack_bf16(reinterpret_cast<const StackSeg*>((char*)d_desc + offs[r]), Lx.nseg, Lx.total,
-                                     Lx.has_sym, (int)(Lx.total < 256 ? Lx.total : 256), s));
+                                     Lx.has_sym, (int)std::min<long long>(Lx.total, device_cus()), s));
             continue;
         }
         const int grid = (int)(Lx.total < 1024 ? Lx.total : 1024);

@@ -20,6 +20,8 @@
 #include "wv_device.h"
 #include "wv_internal.h"
 
+#include <atomic>
+
 namespace wv {
 namespace {
 
@@ -266,17 +268,20 @@ __global__ __launch_bounds__(64 * NWV) void lift_fused_k(const VecLayer L1, cons
 }
 
 template <int C, int OH, int OW, int NWV>
-long long lift_resident() {
-    static long long n = 0;
+long long lift_resident() {   // resident workgroups, cached per device (256 if unknown)
+    static std::atomic<long long> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    long long n = cache[dev].load(std::memory_order_relaxed);
     if (n == 0) {
-        int per_cu = 0, cus = 0, dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int per_cu = 0, cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lift_fused_k<C, OH, OW, NWV>, 64 * NWV, 0) !=
                 hipSuccess ||
             per_cu < 1)
             return 256;
         n = (long long)per_cu * cus;
+        cache[dev].store(n, std::memory_order_relaxed);
     }
     return n;
 }

@@ -30,6 +30,8 @@
 #include "wv_device.h"
 #include "wv_internal.h"
 
+#include <atomic>
+
 namespace wv {
 namespace {
 
@@ -342,14 +344,18 @@ hipError_t launch_lift_rows(const VecLayer& L1, const MfmaLayer& L2, const VecLa
     if ((long long)N * h * w == 0 || nstrips == 0) return hipSuccess;
     if (nstrips < 0 || (long long)(nstrips - 1) * OUTW >= w) return hipErrorInvalidValue;
     if (L1.ch != LC || L2.cin != LC || L2.nbt != 2) return hipErrorInvalidValue;
-    static int resident = 0;
+    // resident workgroups, cached per device
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    int resident = cache[dev].load(std::memory_order_relaxed);
     if (resident == 0) {
-        int per_cu = 0, cus = 0, dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        int per_cu = 0, cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, lift_rows_k, 512, 0) != hipSuccess || per_cu < 1)
             return hipErrorInvalidValue;
         resident = per_cu * cus;
+        cache[dev].store(resident, std::memory_order_relaxed);
     }
     const long long cols = (long long)nstrips * N;
     int seg_rows = h;

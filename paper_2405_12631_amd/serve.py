@@ -19,8 +19,10 @@ Symbols come from one of two places:
 * host coder (coder=True): the iteration's tables are trimmed on the device
   (wv_cdf_trim), copied to the host in two transfers, the rANS streams of every
   request are decoded by a thread pool, and the symbols go back in one
-  transfer.  The run then reports the PCIe bytes moved and the coder threads'
-  busy time.
+  transfer.  The active requests then form two cohorts that alternate: while
+  the GPU computes one cohort's step, the host copies and decodes the other's
+  tables, so GPU, PCIe and coder work overlap.  The run reports the PCIe bytes
+  moved and the coder threads' busy time.
 """
 import ctypes
 import time
@@ -141,30 +143,19 @@ class Slot:
             self.xhat = []
 
 
-class Server:
-    """FIFO admission by footprint, continuous batching, one coding step per iteration."""
+class _StepBuffers:
+    """The step buffers shared by the requests of one iteration (one per cohort with the host
+    coder), grown between iterations when needed: parameters, CDF rows and, with the coder,
+    the trimmed tables, symbols and their pinned host copies."""
 
-    def __init__(self, model, budget_bytes, staging_bytes=16 << 20, on_params=None, coder=False,
-                 coder_threads=16):
-        self.model = model
-        self.budget = budget_bytes
-        self.on_params = on_params      # optional hook(slot, group, subband, step, params) for checks
-        self.coder = coder
-        self.staging = [torch.empty(staging_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
-        self.desc = [torch.empty(staging_bytes, dtype=torch.uint8, device=model.device) for _ in range(2)]
-        self.staging_ev = [None, None]
-        self.rows_cap = 0
-        self.pool = ThreadPoolExecutor(max_workers=coder_threads) if coder else None
-        self.coder_threads = coder_threads
-        self.d2h = self.h2d = 0
-        self.coder_busy = 0.0
+    def __init__(self, model, coder):
+        self.model, self.coder, self.cap = model, coder, 0
 
-    def _grow(self, rows):
-        """Shared step buffers for `rows` rows (grown between iterations when needed)."""
-        if rows <= self.rows_cap:
+    def grow(self, rows):
+        if rows <= self.cap:
             return
         m, dev = self.model, self.model.device
-        cap = max(rows, 2 * self.rows_cap)
+        cap = max(rows, 2 * self.cap)
         self.params = torch.empty(cap * 3 * m.cfg["mix_k"], dtype=torch.float32, device=dev)
         self.cdf = torch.empty(cap * (m.nsym + 1), dtype=torch.int16, device=dev)
         if self.coder:
@@ -175,15 +166,41 @@ class Server:
             self.trim_scratch = torch.empty(max(tb.value, 8), dtype=torch.uint8, device=dev)
             self.sym = torch.empty(cap, dtype=torch.uint8, device=dev)
             self.sym_h = torch.empty(cap, dtype=torch.uint8, pin_memory=True)
-        self.rows_cap = cap
+            self.lolen_h = torch.empty(2 * cap, dtype=torch.uint8, pin_memory=True)
+            self.packed_h = torch.empty(cap * (m.nsym - 1), dtype=torch.int16, pin_memory=True)
+        self.cap = cap
 
-    def step(self, slots, k):
-        """One iteration over the active slots using staging buffer k."""
+
+class Server:
+    """FIFO admission by footprint, continuous batching, one coding step per iteration (with the
+    host coder: per cohort, the two cohorts alternating)."""
+
+    def __init__(self, model, budget_bytes, staging_bytes=16 << 20, on_params=None, coder=False,
+                 coder_threads=16):
+        self.model = model
+        self.budget = budget_bytes
+        self.on_params = on_params      # optional hook(slot, group, subband, step, params) for checks
+        self.coder = coder
+        self.staging = [torch.empty(staging_bytes, dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        self.desc = [torch.empty(staging_bytes, dtype=torch.uint8, device=model.device) for _ in range(2)]
+        self.staging_ev = [None, None]
+        self.bufs = [_StepBuffers(model, coder) for _ in range(2 if coder else 1)]
+        self.pool = ThreadPoolExecutor(max_workers=coder_threads) if coder else None
+        self.copy_stream = torch.cuda.Stream() if coder else None   # table copies to the host
+        self.coder_threads = coder_threads
+        self.d2h = self.h2d = 0
+        self.coder_busy = 0.0
+
+    def _launch(self, slots, k, kb):
+        """Context parameters and CDF tables of one coding step of `slots` (GPU, asynchronous),
+        with staging buffer k and step buffers kb; with the coder also the device trim.
+        Returns the per-slot row offsets and counts."""
         m = self.model
         K = m.cfg["mix_k"]
+        bf = self.bufs[kb]
         rows = [s.rows() for s in slots]
         total = sum(sum(r) for r in rows)
-        self._grow(max(total, 1))
+        bf.grow(max(total, 1))
         items, first = [], []
         at = 0
         for s, rs in zip(slots, rows):
@@ -191,7 +208,7 @@ class Server:
             for b, ws in enumerate(s.ws):
                 items.append(L.wv_step_item(ws.H, ws.W, ws.N, s.q[b].data_ptr(), ws.state.data_ptr(),
                                             ws.scratch.data_ptr(), s.i, s.g,
-                                            self.params.data_ptr() + 4 * at * 3 * K))
+                                            bf.params.data_ptr() + 4 * at * 3 * K))
                 fs.append(at)
                 at += rs[b]
             first.append(fs)
@@ -209,34 +226,60 @@ class Server:
         if self.on_params is not None:
             for s, fs, rs in zip(slots, first, rows):
                 for b, ws in enumerate(s.ws):
-                    prm = self.params[fs[b] * 3 * K:(fs[b] + rs[b]) * 3 * K]
+                    prm = bf.params[fs[b] * 3 * K:(fs[b] + rs[b]) * 3 * K]
                     self.on_params(s, b, s.i, s.g, prm.view(ws.N, rs[b] // ws.N, 3 * K))
         if total:
-            codec.cdf_tables(m, self.params[:total * 3 * K], out=self.cdf)
+            codec.cdf_tables(m, bf.params[:total * 3 * K], out=bf.cdf)
+        tables = None
         if self.coder and total:
-            self._decode_symbols(slots, first, rows, total)
+            cdf = bf.cdf[:total * (m.nsym + 1)].view(total, m.nsym + 1)
+            L.call("wv_cdf_trim", codec._ptr(cdf), total, m.nsym, codec._ptr(bf.lolen), codec._ptr(bf.packed),
+                   bf.packed.numel(), codec._ptr(bf.trim_scratch), bf.trim_scratch.numel(), codec._stream())
+            tables = torch.cuda.Event()
+            tables.record(torch.cuda.current_stream())
+        return dict(slots=slots, first=first, rows=rows, total=total, kb=kb, tables=tables)
+
+    def _complete(self, st):
+        """Symbols of a launched step (from the prepared input, or decoded by the host coder
+        from its trimmed tables), scattered into each slot's q; advances the slots and returns
+        those that finished their last step."""
+        m = self.model
+        slots, first, rows, total, bf = st["slots"], st["first"], st["rows"], st["total"], self.bufs[st["kb"]]
+        if self.coder and total:
+            self._decode_symbols(st, bf)
         for s, fs, rs in zip(slots, first, rows):
             for b, ws in enumerate(s.ws):
                 if not rs[b]:
                     continue
-                sym = self.sym[fs[b]:fs[b] + rs[b]] if self.coder else s.prep.groups[b][4][s.i][s.g]
+                sym = bf.sym[fs[b]:fs[b] + rs[b]] if self.coder else s.prep.groups[b][4][s.i][s.g]
                 codec.scatter_symbols(m, sym, s.q[b], ws, s.i, s.g)
         return [s for s in slots if s.advance()]
 
-    def _decode_symbols(self, slots, first, rows, total):
-        """Host coder for one iteration: trim every row on the device, copy the trimmed
-        tables to the host, decode each request's streams on the thread pool, copy the
-        symbols back."""
+    def step(self, slots, k):
+        """One iteration over the active slots using staging buffer k (coder elided)."""
+        return self._complete(self._launch(slots, k, 0))
+
+    def _decode_symbols(self, st, bf):
+        """Host coder for one launched step: copy the trimmed tables to the host on the copy
+        stream once the trim has run (the compute stream meanwhile runs the other cohort),
+        decode each request's streams on the thread pool, copy the symbols back on the
+        compute stream ahead of the scatter."""
         m = self.model
-        cdf = self.cdf[:total * (m.nsym + 1)].view(total, m.nsym + 1)
-        L.call("wv_cdf_trim", codec._ptr(cdf), total, m.nsym, codec._ptr(self.lolen), codec._ptr(self.packed),
-               self.packed.numel(), codec._ptr(self.trim_scratch), self.trim_scratch.numel(), codec._stream())
-        lolen = self.lolen[:2 * total].cpu().numpy()
+        slots, first, rows, total = st["slots"], st["first"], st["rows"], st["total"]
+        cs = self.copy_stream
+        cs.wait_event(st["tables"])
+        with torch.cuda.stream(cs):
+            bf.lolen_h[:2 * total].copy_(bf.lolen[:2 * total], non_blocking=True)
+        cs.synchronize()
+        lolen = bf.lolen_h[:2 * total].numpy()
         npk = int(lolen[1::2].astype(np.int64).sum())
-        packed = self.packed[:npk].cpu().numpy().view(np.uint16)
+        with torch.cuda.stream(cs):
+            bf.packed_h[:npk].copy_(bf.packed[:npk], non_blocking=True)
+        cs.synchronize()
+        packed = bf.packed_h[:npk].numpy().view(np.uint16)
         self.d2h += lolen.nbytes + packed.nbytes
         tr = codec.Trimmed(lolen, packed, m.nsym)
-        out = self.sym_h.numpy()
+        out = bf.sym_h.numpy()
 
         def work(a, b, data):
             t0 = time.perf_counter()
@@ -254,7 +297,7 @@ class Server:
                     a = fs[b] + n * per
                     futs.append(self.pool.submit(work, a, a + per, streams[n][s.i][s.g]))
         self.coder_busy += sum(f.result() for f in futs)
-        self.sym[:total].copy_(self.sym_h[:total], non_blocking=True)
+        bf.sym[:total].copy_(bf.sym_h[:total], non_blocking=True)
         self.h2d += total
 
     def run(self, requests, preps, admit_until=None, max_seconds=120.0, log=None, keep_outputs=False,
@@ -277,6 +320,8 @@ class Server:
         self.coder_busy = 0.0
         fp = {pid: footprint(m, p, self.coder) for pid, p in preps.items()}
         vclock = 0.0
+        inflight = [None, None]   # host coder: the launched, not yet decoded step of each cohort
+        turn = 0                  # host coder: the cohort launched in this iteration
         while True:
             now = vclock if tick is not None else time.perf_counter() - t0
             while pending and pending[0][0] <= now and (admit_until is None or pending[0][0] <= admit_until):
@@ -289,18 +334,32 @@ class Server:
             while queue and used + fp[queue[0][1]] <= self.budget:
                 t_arr, pid = queue.popleft()
                 slot = Slot(m, dict(arrival=t_arr, prep=pid, admitted=now), preps[pid])
+                slot.cohort = turn
                 mid_joins += any((a.i, a.g) != (0, 0) for a in active)
                 used += fp[pid]
                 active.append(slot)
             peak_active = max(peak_active, len(active))
-            if active:
+            fin = []
+            if self.coder:
+                # Launch this cohort's step, then decode the other cohort's tables (launched in
+                # the previous iteration) while the GPU computes.
+                mine = [s_ for s_ in active if s_.cohort == turn]
+                if mine:
+                    inflight[turn] = self._launch(mine, turn, turn)
+                if inflight[1 - turn] is not None:
+                    fin = self._complete(inflight[1 - turn])
+                    inflight[1 - turn] = None
+                if mine or fin:
+                    iters += 1
+                turn ^= 1
+            elif active:
                 fin = self.step(active, k)
                 k ^= 1
                 iters += 1
-                for s in fin:
-                    s.finish(m)
-                    active.remove(s)
-                    finishing.append(s)
+            for s in fin:
+                s.finish(m)
+                active.remove(s)
+                finishing.append(s)
             for s in list(finishing):
                 if tick is not None:
                     s.done_event.synchronize()
