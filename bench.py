@@ -72,7 +72,7 @@ def measured_traffic(precision):
 # plain 1 GiB device copy; averaged over the 117 launches of three batch decodes.  Valid only for
 # the kernel source with this sha256 (else the line reports null).
 STACK_TRAFFIC_SOURCE = ("paper_2405_12631_amd/csrc/wv_stack_bf16.hip",
-                        "caac903634ea7f485952e36b944733fcd610713c7d026a0aa39ceda22c722971")
+                        "2a500d5ec4b7822e523f3ffaa2a2ffb03f6a8cd2ff8c9b7a9fd9d42a21362d17")
 STACK_TRAFFIC_BYTES_PER_LAUNCH = 1968.67e6
 
 

@@ -29,13 +29,12 @@
 // same tanh), so the two kernels give identical arrays.
 #include "wv_device.h"
 #include "wv_internal.h"
+#include "wv_rows.h"
 
 #include <atomic>
 
 namespace wv {
 namespace {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int LC = 32;            // filter channels
 constexpr int NPOS = 128;         // middle-layer positions per row computed: 8 M blocks
@@ -47,18 +46,7 @@ constexpr int PB = LC * 4;        // bytes per position in the layer rings (8 ch
 constexpr int R1 = 4, R2 = 5, RZ = 8;
 constexpr int NST = 9 * (LC / 16);   // (tap, 16-channel chunk) steps of the middle layer
 
-// Chunk c of slot s at chunk c ^ (s & 7): the MFMA fragment reads of 8 neighbouring
-// positions then cover all banks.
-__device__ __forceinline__ int swz(int slot, int chunk) { return (slot * 8 + (chunk ^ (slot & 7))) * 16; }
-__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 __device__ __forceinline__ int rmod(int r, int n) { return (r + 8 * n) % n; }   // r >= -8 n
-
-// LDS-only workgroup barrier: global loads and stores stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 struct Item {
     int n, y0, R, c0;

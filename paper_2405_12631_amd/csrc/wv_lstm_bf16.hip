@@ -18,14 +18,10 @@
 // activations and cell arithmetic, so both forms give identical h and c.
 #include "wv_device.h"
 #include "wv_internal.h"
+#include "wv_rows.h"
 
 namespace wv {
 namespace {
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float floatx2 __attribute__((ext_vector_type(2)));
 
 constexpr int SW = LSTM_STRIP;     // output positions per row (4 blocks of 16)
 constexpr int SLOTS = SW + 2;      // ring slots: slot k is column c0 - 1 + k
@@ -35,22 +31,6 @@ constexpr int NCH = 64;
 constexpr int NK = 18;             // K steps: 9 taps x 2 chunks of 32 channels
 constexpr int NBT = 16;            // 16-column blocks of the 256 gate columns
 constexpr int NV = SLOTS * 8;      // 16-byte pieces of an input row (528)
-
-__device__ __forceinline__ int swz(int slot, int chunk) { return (slot * 8 + (chunk ^ (slot & 7))) * 16; }
-__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
-__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){lo, hi}, bf16x2));
-}
-__device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ __forceinline__ floatx4 mfma(uint4 a, uint4 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
-}
-__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 // Packed gate column (block, column) of channel ch and gate g: the layer's packing puts
 // gate g of channels 16 k .. 16 k + 15 in block 4 k + g.
@@ -110,7 +90,7 @@ __device__ __forceinline__ void row_gates(const uint8_t* ring, const uint16_t (*
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[mb][j] = mfma(wr[st][j], a[st % 3][mb], acc[mb][j]);
+            for (int j = 0; j < 2; ++j) acc[mb][j] = mfma_bf16(wr[st][j], a[st % 3][mb], acc[mb][j]);
         if (st + 2 < NK) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
     }
@@ -126,7 +106,7 @@ __device__ __forceinline__ void row_gates(const uint8_t* ring, const uint16_t (*
         const uint4 av = make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
                                     e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[mb][j] = mfma(ws[j], av, acc[mb][j]);
+        for (int j = 0; j < 2; ++j) acc[mb][j] = mfma_bf16(ws[j], av, acc[mb][j]);
     }
 }
 

@@ -35,41 +35,19 @@
 // parameters.
 #include "wv_device.h"
 #include "wv_internal.h"
+#include "wv_rows.h"
 
 namespace wv {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 constexpr int SW = 64;             // positions a layer computes per row (4 blocks of 16)
 constexpr int SLOTS = SW + 2;      // ring columns; slot k is image column c0 - 4 + k
 constexpr int PSTR = 128;          // bytes per slot: 64 BF16 channels in 8 chunks of 16 bytes
-// Chunk c of slot s is stored at chunk c ^ (s & 7): the fragment reads of 8 neighbouring
-// positions then spread over all banks (measured: 164 B/clk per CU for the fragment
-// pattern, against 117 with a 16-byte pad per slot and 64 unpadded).
-__device__ __forceinline__ int swz(int slot, int chunk) { return (slot * 8 + (chunk ^ (slot & 7))) * 16; }
 constexpr int RROW = SLOTS * PSTR;
 constexpr int RING = 4 * RROW;
 constexpr int NCH = 64;            // channels of every layer input
 constexpr int CC = NCH / 32;       // K chunks per tap
 constexpr int NK = 9 * CC;         // K steps per layer
-
-__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even (v_cvt_pk_bf16_f32)
-    return __builtin_bit_cast(uint16_t, (__bf16)f);
-}
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float floatx2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {   // two values, one instruction
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatx2){lo, hi}, bf16x2));
-}
-__device__ __forceinline__ bf16x8 as_bf(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
-__device__ __forceinline__ floatx4 mfma(uint4 a, uint4 b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
-}
-
-// Lane index within the wave, computed where it is used (each wave role keeps its own).
-__device__ __forceinline__ int lane_id() { return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
 struct Item {
     int n, y0, R, c0;
@@ -123,7 +101,7 @@ __device__ __forceinline__ void row_mfma(const uint8_t* rin, int x, int mb0, con
 #pragma unroll
         for (int mb = 0; mb < MBN; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(wr[st][nb], a[st & 1][mb], acc[mb][nb]);
+            for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma_bf16(wr[st][nb], a[st & 1][mb], acc[mb][nb]);
         // Keep the next step's fragment reads ahead of this step's MFMAs (two fragment sets
         // live): the latency of an LDS read is then covered by a step of MFMAs.
         if (st + 1 < NK) __builtin_amdgcn_sched_group_barrier(0x100, MBN, 0);
@@ -151,17 +129,9 @@ __device__ __forceinline__ void row_sym(const uint16_t (*rs)[SLOTS], int x, cons
         const uint4 av = make_uint4(e[0] | ((uint32_t)e[1] << 16), e[2] | ((uint32_t)e[3] << 16),
                                     e[4] | ((uint32_t)e[5] << 16), e[6] | ((uint32_t)e[7] << 16));
 #pragma unroll
-        for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma(ws[nb], av, acc[mb][nb]);
+        for (int nb = 0; nb < NBL; ++nb) acc[mb][nb] = mfma_bf16(ws[nb], av, acc[mb][nb]);
         __builtin_amdgcn_sched_barrier(0);   // one block's symbol reads at a time (register budget)
     }
-}
-
-// Workgroup barrier that orders LDS only: a wave's global loads (the next input row) and
-// stores (parameters) stay in flight across it, where __syncthreads would wait for them.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 struct Rings {
