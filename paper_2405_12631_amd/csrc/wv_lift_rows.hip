@@ -186,14 +186,19 @@ __device__ __forceinline__ void vec_role(const VecLayer& L3, CView z, CView A, V
         };
         float zn = zload(I.y0 - 3);
         float an = 0.f;
+        float pend = 0.f;   // the previous step's output value
         for (int t = 0; t < T; ++t) {
+            // What the previous step loaded is used before this step issues a global access:
+            // loads and stores share one completion counter, so a wait for a load placed after
+            // this step's store would also wait for the store.  For the same reason the output
+            // is stored one step late, at the top of the next step.
             // ---- z ring: row y0 - 3 + t ----
-            if (t <= I.R + 5) {
-                if (v < ZN) S.zr[rmod(I.y0 - 3 + t, RZ)][v] = zn;
-                if (t + 1 <= I.R + 5) zn = zload(I.y0 - 2 + t);
-            }
+            if (t <= I.R + 5 && v < ZN) S.zr[rmod(I.y0 - 3 + t, RZ)][v] = zn;
+            const float acur = an;   // A of this step's output row
+            wait_vm();
+            if (t >= 11 && owner) op[(long long)(I.y0 - 11 + t) * out.rs + (long long)oc * out.cs] = pend;
+            if (t + 1 <= I.R + 5) zn = zload(I.y0 - 2 + t);
             // ---- A of the next step's output row ----
-            const float acur = an;
             if (t + 1 >= 10 && t + 1 <= I.R + 9) an = aload(I.y0 - 9 + t);
             // ---- layer 1 on row y0 - 5 + t: tasks (position a, 16-channel half) ----
             if (t >= 3 && t <= I.R + 6) {
@@ -286,11 +291,12 @@ __device__ __forceinline__ void vec_role(const VecLayer& L3, CView z, CView A, V
                     const float zz = S.zr[rmod(r3, RZ)][o + 3];
                     float f = predict ? zz + vv : 0.5f * zz + vv;
                     if (lift_int) f = rintf(f);
-                    op[(long long)r3 * out.rs + (long long)oc * out.cs] = acur + sign * f;
+                    pend = acur + sign * f;
                 }
             }
             lds_barrier();
         }
+        if (owner) op[(long long)(I.y0 + I.R - 1) * out.rs + (long long)oc * out.cs] = pend;   // t = T - 1
     }
 }
 

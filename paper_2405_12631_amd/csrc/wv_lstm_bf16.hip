@@ -149,6 +149,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void l
                 ws[j] = ld_g(reinterpret_cast<const uint4*>(S.wsym) + src);
             }
             if (tid < 4 * NCH) bias_s[tid] = gmem(S.bias)[pblock(tid >> 2, tid & 3) * 16 + ((tid >> 2) & 15)];
+            wait_vm();
         }
         // ---- input rows: thread tid owns 16-byte pieces tid and tid + 512 of a row ----
         const int win = S.w >> S.up;
@@ -247,9 +248,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void l
         };
         for (int t = 0; t < T; ++t) {
             const int x = I.y0 - 3 + t;   // output row of this step
+            // Everything loaded in the previous step goes to LDS before this step issues any
+            // global access: loads and stores share one completion counter, so a wait placed
+            // after this step's loads and stores would wait for those too.
             if (t <= I.R + 1) store(I.y0 - 1 + t);
-            if (t <= I.R) load(I.y0 + t);
             if (t >= 2 && t <= I.R + 1) cstore(x + 1);
+            wait_vm();   // already true here (the previous step's stores are a step old); it
+                         // keeps later register reuse in this step from waiting on new loads
+            if (t <= I.R) load(I.y0 + t);
             if (t >= 1 && t <= I.R) cload(I.y0 - 1 + t);
             if (t >= 4) flush(x - 1);
             if (t >= 3) {

@@ -32,6 +32,12 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// s_waitcnt vmcnt(0): every global load and store of the wave has completed.  Loads and
+// stores share that counter, so once both are in flight the compiler can only wait for all
+// of them; after values loaded ahead of a loop (weights, biases) it marks them complete
+// here, where nothing else is in flight, instead of on their first use inside the loop.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }
+
 // FP32 -> BF16, round to nearest even (v_cvt_pk_bf16_f32); two values in one instruction.
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
