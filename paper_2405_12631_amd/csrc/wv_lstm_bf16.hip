@@ -138,7 +138,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void l
         const LstmSeg& S = segs[si];
         if (S.wt != wcur) {   // every segment of a launch has the same weights
             wcur = S.wt;
-            const int r = lane & 15, kk = lane >> 4;
+            int ln = lane;   // opaque: the lane offsets below are not kept across the loops
+            asm volatile("" : "+v"(ln));
+            const int r = ln & 15, kk = ln >> 4;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int ch = 8 * wv + 2 * (r >> 2) + j;
@@ -255,17 +257,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void l
             if (t >= 2 && t <= I.R + 1) cstore(x + 1);
             wait_vm();   // already true here (the previous step's stores are a step old); it
                          // keeps later register reuse in this step from waiting on new loads
-            if (t <= I.R) load(I.y0 + t);
-            if (t >= 1 && t <= I.R) cload(I.y0 - 1 + t);
-            if (t >= 4) flush(x - 1);
+            // This step's global accesses: waves 0-3 issue theirs first, waves 4-7 (the other
+            // wave of each SIMD) between the two halves of the row, so that one wave of a SIMD
+            // issues MFMAs while the other waits on the memory pipeline.
+            auto vmem = [&]() {
+                if (t <= I.R) load(I.y0 + t);
+                if (t >= 1 && t <= I.R) cload(I.y0 - 1 + t);
+                if (t >= 4) flush(x - 1);
+            };
+            if (wv < 4) vmem();
+            if (t < 3 && wv >= 4) vmem();   // no rows computed in this step
             if (t >= 3) {
                 const uint8_t* cin = cin_s[x & 1];
                 uint8_t* cout = cout_s[x & 1];
                 uint8_t* hout = hout_s[x & 1];
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
+                    if (half == 1 && wv >= 4) vmem();
                     floatx4 acc[2][2];
+                    // The gate MFMAs at raised wave priority, the cell update at the normal one:
+                    // a wave in its MFMAs goes first, and the other wave's epilogue fills the
+                    // issue slots between them.
+                    __builtin_amdgcn_s_setprio(1);
                     row_gates(ring, ring_s, x, 2 * half, wr, ws, acc, lane);
+                    __builtin_amdgcn_s_setprio(0);
                     const int ln = opaque(lane);
                     const int ch0 = 8 * wv + 2 * (ln >> 4);   // this lane's two channels
 #pragma unroll
