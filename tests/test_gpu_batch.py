@@ -228,14 +228,15 @@ def test_fused_step_stacks_equal_layer_by_layer_bitwise():
     layer-by-layer launches, bit for bit: the parameters of every (subband, step) and the
     ConvLSTM's h and c after every subband, on a plan with tall subbands split into row pieces
     (1088 x 1920: level 1 is 544 rows in five pieces, 17 stack strips with a ragged last one),
-    a 256 x 256 image and a small ragged one."""
+    a 256 x 256 image, a small ragged one and a 16 x 32 one (level-4 subbands of 1 x 2: items of
+    one row)."""
     import os
     need_gpu()
     from paper_2405_12631_amd import codec, batch as B, WV_BF16
     say("fused stacks vs layer by layer")
     cfg = get_config("ycbcr512x768")
     model = codec.Model(cfg, pack_weights(cfg, make_weights(cfg)), precision=WV_BF16)
-    sizes = [(1088, 1920), (256, 256), (48, 80)]
+    sizes = [(1088, 1920), (256, 256), (48, 80), (16, 32)]
     imgs = _images(sizes, seed=61)
     os.environ["WV_FUSED_STACKS"] = "0"
     try:
