@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <array>
 #include <atomic>
 #include <mutex>
 #include <string>
@@ -1362,18 +1363,60 @@ bool stack_fusable(const wv_model* m) {
            3 * m->cfg.mix_k <= 16;
 }
 
-// Rows per work item of a fused launch: whole strips up to 128 rows, else even pieces of
-// at most 128 rows (each piece recomputes 3 rows of context above and below).
-int stack_seg_rows(int h) {
-    const int pieces = (h + 127) / 128;
+// Rows per work item of a fused launch: whole strips up to cap rows, else even pieces of at
+// most cap rows (each piece of a step stack recomputes 3 rows of context above and below; a
+// piece of any height gives the same outputs).
+int stack_seg_rows(int h, int cap = 128) {
+    const int pieces = (h + cap - 1) / cap;
     return (h + pieces - 1) / pieces;
+}
+
+// The piece cap of a fused launch over several plane groups' subbands (h, w, planes each):
+// the one among a few candidates that minimises the most row steps a resident workgroup
+// walks.  Items are dealt round-robin in the kernels' order (strip fastest, then piece,
+// then plane, group after group) and a piece of R rows costs R + fill row steps (fill: 10
+// for a step stack, 3 for the ConvLSTM).  On the 64-image batch this takes the critical
+// path of the stack launches 3 % and of the ConvLSTM launches 4 % below a fixed 128.
+int fused_seg_cap(const std::vector<std::array<int, 3>>& shapes, int strip, int fill) {
+    static const int caps[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024};
+    const long long cus = device_cus();
+    int best_cap = 128;
+    long long best = -1;
+    std::vector<long long> load;
+    for (int cap : caps) {
+        long long total = 0;
+        for (const auto& sh : shapes) {
+            const int sr = stack_seg_rows(sh[0], cap);
+            total += (long long)((sh[1] + strip - 1) / strip) * ((sh[0] + sr - 1) / sr) * sh[2];
+        }
+        if (total == 0) return 128;
+        const long long g = std::min<long long>(total, cus);
+        load.assign((size_t)g, 0);
+        long long k = 0;
+        for (const auto& sh : shapes) {
+            const int h = sh[0], sr = stack_seg_rows(h, cap), sy = (h + sr - 1) / sr;
+            const int sx = (sh[1] + strip - 1) / strip;
+            for (int n = 0; n < sh[2]; ++n)
+                for (int y = 0; y < sy; ++y) {
+                    const long long cost = std::min(sr, h - y * sr) + fill;
+                    for (int x = 0; x < sx; ++x, ++k) load[(size_t)(k % g)] += cost;
+                }
+        }
+        const long long worst = *std::max_element(load.begin(), load.end());
+        if (best < 0 || worst < best) {
+            best = worst;
+            best_cap = cap;
+        }
+    }
+    return best_cap;
 }
 
 // Fused step-stack segment of a plane group's subband S at step g: input l_i = hcur
 // (BF16 NHWC), symbols of this subband (plane 0) at q_sub with plane stride q_ps.
 // Returns the segment's work items (0 for a step with no positions).
 long long make_stack_seg(const wv_model* m, int type, int g, const float* hcur, const Sub& S, int nplanes,
-                         const int16_t* q_sub, long long q_ps, float* params, long long item0, StackSeg& sg) {
+                         const int16_t* q_sub, long long q_ps, float* params, long long item0, StackSeg& sg,
+                         int cap = 128) {
     const std::vector<MfmaLayer16>& Ls = m->ctx16[type][g];
     sg = StackSeg{};
     for (int l = 0; l < 4; ++l) {
@@ -1393,7 +1436,7 @@ long long make_stack_seg(const wv_model* m, int type, int g, const float* hcur, 
     sg.K = m->cfg.mix_k;
     sg.sigma_min = m->cfg.sigma_min;
     sg.strips_x = (S.w + STACK_STRIP - 1) / STACK_STRIP;
-    sg.seg_rows = stack_seg_rows(S.h);
+    sg.seg_rows = stack_seg_rows(S.h, cap);
     sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
     sg.item0 = item0;
     if (wv_group_count(S.h, S.w, g) == 0) {   // a 1-wide subband's empty step
@@ -1407,7 +1450,8 @@ long long make_stack_seg(const wv_model* m, int type, int g, const float* hcur, 
 // halves start at d_state (SS floats each: h then c), symbols at q (plane stride q_ps);
 // Pv is the previous subband (null for the first).  Returns the segment's work items.
 long long make_lstm_seg(const wv_model* m, int i, const Sub& S, const Sub* Pv, float* d_state, size_t SS,
-                        int nplanes, const int16_t* q, long long q_ps, long long item0, LstmSeg& sg) {
+                        int nplanes, const int16_t* q, long long q_ps, long long item0, LstmSeg& sg,
+                        int cap = 128) {
     const int C = m->cfg.ctx_ch;
     sg = LstmSeg{};
     sg.wt = m->lstm16.w;
@@ -1431,7 +1475,7 @@ long long make_lstm_seg(const wv_model* m, int i, const Sub& S, const Sub* Pv, f
     sg.h = S.h;
     sg.w = S.w;
     sg.strips_x = (S.w + LSTM_STRIP - 1) / LSTM_STRIP;
-    sg.seg_rows = stack_seg_rows(S.h);
+    sg.seg_rows = stack_seg_rows(S.h, cap);
     sg.segs_y = (S.h + sg.seg_rows - 1) / sg.seg_rows;
     sg.item0 = item0;
     return (long long)sg.strips_x * sg.segs_y * nplanes;
@@ -1492,13 +1536,17 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 pl.seg_off = host.size();
                 pl.nseg = ng;
                 pl.fused = 2;
+                std::vector<std::array<int, 3>> shapes;
+                for (int b = 0; b < ng; ++b)
+                    shapes.push_back({P->lay[b][i].h, P->lay[b][i].w, groups[b].nplanes});
+                const int cap = fused_seg_cap(shapes, LSTM_STRIP, 3);
                 long long item = 0;
                 for (int b = 0; b < ng; ++b) {
                     const wv_group& G = groups[b];
                     LstmSeg sg;
                     item += make_lstm_seg(m, i, P->lay[b][i], i > 0 ? &P->lay[b][i - 1] : nullptr, G.d_state,
                                           state_floats(m->cfg, G.nplanes, G.H, G.W), G.nplanes, G.d_q,
-                                          (long long)G.H * G.W, item, sg);
+                                          (long long)G.H * G.W, item, sg, cap);
                     const size_t at = host.size();
                     host.resize(at + sizeof(LstmSeg));
                     memcpy(host.data() + at, &sg, sizeof sg);
@@ -1622,6 +1670,11 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 pl.nseg = ng;
                 pl.fused = 1;
                 pl.has_sym = g > 0;
+                std::vector<std::array<int, 3>> shapes;
+                for (int b = 0; b < ng; ++b)   // a step with no positions in a group adds no items
+                    shapes.push_back({P->lay[b][i].h, P->lay[b][i].w,
+                                      wv_group_count(P->lay[b][i].h, P->lay[b][i].w, g) ? groups[b].nplanes : 0});
+                const int cap = fused_seg_cap(shapes, STACK_STRIP, 10);
                 long long item = 0;
                 for (int b = 0; b < ng; ++b) {
                     const wv_group& G = groups[b];
@@ -1630,7 +1683,8 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                     const float* hcur = G.d_state + (size_t)(i & 1) * 2 * SS;
                     StackSeg sg;
                     item += make_stack_seg(m, type, g, hcur, S, G.nplanes, G.d_q + S.off, (long long)G.H * G.W,
-                                           P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr, item, sg);
+                                           P->d_params ? P->d_params + ro[b] * 3 * m->cfg.mix_k : nullptr, item, sg,
+                                           cap);
                     const size_t at = host.size();
                     host.resize(at + sizeof(StackSeg));
                     memcpy(host.data() + at, &sg, sizeof sg);
