@@ -70,11 +70,11 @@ def measured_traffic(precision):
 # HBM bytes per launch of the fused step-stack kernel (steps 1-3) in the 64-image batch, from
 # rocprofv3 FETCH_SIZE (x2.0) + WRITE_SIZE (x1.0), the factors being what each counter reads for a
 # plain 1 GiB device copy; averaged over the 117 launches of three batch decodes.  The halo re-reads
-# depend on the row pieces the library cuts (wv_api.hip) as well as on the kernel, so the figure is
+# depend on the row pieces the library cuts (wv_pieces.h) as well as on the kernel, so the figure is
 # valid only for both sources with these sha256 (else the line reports null).
 STACK_TRAFFIC_SOURCES = {
     "paper_2405_12631_amd/csrc/wv_stack_bf16.hip": "2a500d5ec4b7822e523f3ffaa2a2ffb03f6a8cd2ff8c9b7a9fd9d42a21362d17",
-    "paper_2405_12631_amd/csrc/wv_api.hip": "5579caa7819b9a1c4ec810e6a849e20acef985e177d219ebb743c388d86cf6fa",
+    "paper_2405_12631_amd/csrc/wv_pieces.h": "9f9e06bfff4a72629253e7de473c01d74a8ac2621eaf852631197e02989fae09",
 }
 STACK_TRAFFIC_BYTES_PER_LAUNCH = 1919.3e6
 

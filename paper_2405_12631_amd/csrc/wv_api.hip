@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "wv_internal.h"
+#include "wv_pieces.h"
 
 using namespace wv;
 
@@ -1363,54 +1364,6 @@ bool stack_fusable(const wv_model* m) {
            3 * m->cfg.mix_k <= 16;
 }
 
-// Rows per work item of a fused launch: whole strips up to cap rows, else even pieces of at
-// most cap rows (each piece of a step stack recomputes 3 rows of context above and below; a
-// piece of any height gives the same outputs).
-int stack_seg_rows(int h, int cap = 128) {
-    const int pieces = (h + cap - 1) / cap;
-    return (h + pieces - 1) / pieces;
-}
-
-// The piece cap of a fused launch over several plane groups' subbands (h, w, planes each):
-// the one among a few candidates that minimises the most row steps a resident workgroup
-// walks.  Items are dealt round-robin in the kernels' order (strip fastest, then piece,
-// then plane, group after group) and a piece of R rows costs R + fill row steps (fill: 10
-// for a step stack, 3 for the ConvLSTM).  On the 64-image batch this takes the critical
-// path of the stack launches 3 % and of the ConvLSTM launches 4 % below a fixed 128.
-int fused_seg_cap(const std::vector<std::array<int, 3>>& shapes, int strip, int fill) {
-    static const int caps[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024};
-    const long long cus = device_cus();
-    int best_cap = 128;
-    long long best = -1;
-    std::vector<long long> load;
-    for (int cap : caps) {
-        long long total = 0;
-        for (const auto& sh : shapes) {
-            const int sr = stack_seg_rows(sh[0], cap);
-            total += (long long)((sh[1] + strip - 1) / strip) * ((sh[0] + sr - 1) / sr) * sh[2];
-        }
-        if (total == 0) return 128;
-        const long long g = std::min<long long>(total, cus);
-        load.assign((size_t)g, 0);
-        long long k = 0;
-        for (const auto& sh : shapes) {
-            const int h = sh[0], sr = stack_seg_rows(h, cap), sy = (h + sr - 1) / sr;
-            const int sx = (sh[1] + strip - 1) / strip;
-            for (int n = 0; n < sh[2]; ++n)
-                for (int y = 0; y < sy; ++y) {
-                    const long long cost = std::min(sr, h - y * sr) + fill;
-                    for (int x = 0; x < sx; ++x, ++k) load[(size_t)(k % g)] += cost;
-                }
-        }
-        const long long worst = *std::max_element(load.begin(), load.end());
-        if (best < 0 || worst < best) {
-            best = worst;
-            best_cap = cap;
-        }
-    }
-    return best_cap;
-}
-
 // Fused step-stack segment of a plane group's subband S at step g: input l_i = hcur
 // (BF16 NHWC), symbols of this subband (plane 0) at q_sub with plane stride q_ps.
 // Returns the segment's work items (0 for a step with no positions).
@@ -1539,7 +1492,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 std::vector<std::array<int, 3>> shapes;
                 for (int b = 0; b < ng; ++b)
                     shapes.push_back({P->lay[b][i].h, P->lay[b][i].w, groups[b].nplanes});
-                const int cap = fused_seg_cap(shapes, LSTM_STRIP, 3);
+                const int cap = fused_seg_cap(shapes, LSTM_STRIP, 3, device_cus());
                 long long item = 0;
                 for (int b = 0; b < ng; ++b) {
                     const wv_group& G = groups[b];
@@ -1674,7 +1627,7 @@ static int plan_build(const wv_model* m, int ng, const wv_group* groups, const i
                 for (int b = 0; b < ng; ++b)   // a step with no positions in a group adds no items
                     shapes.push_back({P->lay[b][i].h, P->lay[b][i].w,
                                       wv_group_count(P->lay[b][i].h, P->lay[b][i].w, g) ? groups[b].nplanes : 0});
-                const int cap = fused_seg_cap(shapes, STACK_STRIP, 10);
+                const int cap = fused_seg_cap(shapes, STACK_STRIP, 10, device_cus());
                 long long item = 0;
                 for (int b = 0; b < ng; ++b) {
                     const wv_group& G = groups[b];
@@ -1886,6 +1839,26 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
     launches[2].mode = CONV_RELU;
     for (int l = 1; l < Lc - 1; ++l) launches[2 + l].mode = CONV_RELU;
     launches[fuse0 - 1].mode = CONV_HEAD;
+    // Row-piece caps of the three fused launches, from the shapes of all items (an item the
+    // checks below reject is skipped here).
+    int cap_lstm = 128, cap_st0 = 128, cap_st1 = 128;
+    if (fuse) {
+        std::vector<std::array<int, 3>> sh_l, sh_0, sh_1;
+        for (int k = 0; k < n; ++k) {
+            const wv_step_item& it = items[k];
+            std::vector<Sub> lay;
+            if (it.nplanes < 1 || layout(m->cfg, it.H, it.W, lay) != WV_OK) continue;
+            const int i = it.subband, g = it.step;
+            if (i < 0 || i >= (int)lay.size() || g < 0 || g > 3) continue;
+            const Sub& S = lay[i];
+            if (g == 0) sh_l.push_back({S.h, S.w, it.nplanes});
+            if (wv_group_count(S.h, S.w, g) > 0) (g > 0 ? sh_1 : sh_0).push_back({S.h, S.w, it.nplanes});
+        }
+        const long long cus = device_cus();
+        cap_lstm = fused_seg_cap(sh_l, LSTM_STRIP, 3, cus);
+        cap_st0 = fused_seg_cap(sh_0, STACK_STRIP, 10, cus);
+        cap_st1 = fused_seg_cap(sh_1, STACK_STRIP, 10, cus);
+    }
     std::vector<int> nsubs;   // per item, for the coding-order cursor
     for (int k = 0; k < n; ++k) {
         const wv_step_item& it = items[k];
@@ -1920,7 +1893,7 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
             ItemLaunch& Ll = launches[0];
             LstmSeg sg;
             Ll.total += make_lstm_seg(m, i, S, i > 0 ? &lay[i - 1] : nullptr, it.d_state, SS, it.nplanes, it.d_q, HW,
-                                      Ll.total, sg);
+                                      Ll.total, sg, cap_lstm);
             const size_t at = Ll.segs.size();
             Ll.segs.resize(at + sizeof(LstmSeg));
             memcpy(Ll.segs.data() + at, &sg, sizeof sg);
@@ -1958,7 +1931,8 @@ extern "C" int wv_context_params_items(const wv_model* m, int n, const wv_step_i
         if (fuse) {
             ItemLaunch& Fl = launches[fuse0 + (g > 0)];
             StackSeg sg;
-            Fl.total += make_stack_seg(m, S.type, g, hcur, S, it.nplanes, it.d_q + S.off, HW, it.d_params, Fl.total, sg);
+            Fl.total += make_stack_seg(m, S.type, g, hcur, S, it.nplanes, it.d_q + S.off, HW, it.d_params, Fl.total, sg,
+                                       g > 0 ? cap_st1 : cap_st0);
             const size_t at = Fl.segs.size();
             Fl.segs.resize(at + sizeof(StackSeg));
             memcpy(Fl.segs.data() + at, &sg, sizeof sg);
